@@ -1,0 +1,163 @@
+/*
+ * aolmi.h -- Array-OL repetitive tasks on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the downscaler hot path from Rodrigues, Guyomarc'h, Dekeyser,
+ * "Programming Massively Parallel Architectures using MARTE: a Case Study":
+ * a video downscaler written as Array-OL repetitive tasks (Sec. III-A), i.e.
+ * tilers that take each pattern at origin + paving.r + fitting.i modulo the
+ * array shape, and an elementary per-pattern filter: a horizontal then a
+ * vertical polyphase interpolating filter over every frame and colour plane
+ * (Sec. III).
+ *
+ * General rules
+ *  - Every function returns an aol_status. Functions never throw, abort or
+ *    print; on failure aol_last_error() returns a thread-local message.
+ *  - Device buffers are plain device pointers owned by the caller. Plans own
+ *    the device tables they allocate at creation (filter fragments, tile
+ *    lists, pointer tables) and free them on destroy.
+ *  - Run calls (aol_downscale_u8, aol_downscale_f, aol_batch_run,
+ *    aol_graph_launch, aol_wsum_run) only enqueue work on the given stream:
+ *    they never allocate and never synchronise. They check pointers and
+ *    alignment and report launch errors; faults inside a kernel surface at
+ *    the caller's next synchronisation.
+ *  - Inputs and outputs must not alias.
+ *  - Distinct plans may be used from different threads; one plan is not
+ *    re-entrant (do not run it on two streams at once).
+ *  - Streams are hipStream_t; NULL is the default stream.
+ */
+#ifndef AOLMI_H
+#define AOLMI_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum aol_status {
+  AOL_OK = 0,
+  AOL_ERR_INVALID = -1,     /* bad shape, rank, pointer, pitch or argument */
+  AOL_ERR_UNSUPPORTED = -2, /* legal request outside the implemented limits */
+  AOL_ERR_NOMEM = -3,       /* host or device allocation failed */
+  AOL_ERR_HIP = -4          /* a HIP runtime call failed (see aol_last_error) */
+} aol_status;
+
+typedef enum aol_precision {
+  AOL_PREC_U8 = 0,   /* uint8 pixels, integer taps, bit-exact fixed point */
+  AOL_PREC_BF16 = 1, /* bfloat16 normalised pixels in, float32 out (MFMA) */
+  AOL_PREC_FP16 = 2  /* float16 normalised pixels in, float32 out (MFMA) */
+} aol_precision;
+
+/* Implementation limits (AOL_ERR_UNSUPPORTED beyond these). */
+#define AOL_MAX_P 16        /* output phases per repetition */
+#define AOL_MAX_Q 64        /* input pixels per repetition */
+#define AOL_MAX_TAPS 32     /* taps per phase */
+#define AOL_MAX_COEFF 2047  /* |c| for integer taps */
+#define AOL_MAX_PLANES 4    /* planes per downscale plan */
+#define AOL_MAX_RANK 4      /* ranks of generic tilers */
+
+/* Thread-local text of the last error (never NULL; empty after success). */
+const char* aol_last_error(void);
+
+/* Library version, "major.minor.patch". */
+const char* aol_version(void);
+
+/* --------------------------------------------------------------------------
+ * One axis of the downscaler: a polyphase interpolating filter.
+ *
+ * Sec. III: the horizontal filter reduces each line (352 -> 132 pixels in the
+ * paper's CIF case) and the vertical filter reduces the lines (288 -> 128),
+ * each by interpolating packets of input pixels. Sec. III-A: the horizontal
+ * task has multiplicity [288, 44], one elementary task per line and packet.
+ * Here a repetition r consumes a packet of q input pixels and emits p output
+ * pixels; on an axis of length N there are R = ceil(N/q) repetitions and
+ * M = p*R outputs. Output o = p*r + phi (phase phi < p) is
+ *
+ *   acc = sum_{k<taps} coeff[phi*taps + k] * x[(q*r + s_phi + k) mod N]
+ *
+ * integer path: out = clamp(floor((acc + 128) / 256), 0, 255);
+ * float path:   out = acc / 256 evaluated in float (no clamp).
+ *
+ * The paper gives no coefficients, tap count or window placement; they are
+ * caller data. phase_start (host, p entries) gives s_phi; NULL selects the
+ * pixel-centre default s_phi = floor(((2phi+1)q - p) / (2p)) - floor((taps-1)/2),
+ * see aol_default_phase_starts. coeff is host memory, p*taps int16, row-major
+ * [phase][tap]; it is copied at plan creation.
+ * ------------------------------------------------------------------------ */
+typedef struct aol_polyphase {
+  int32_t p;
+  int32_t q;
+  int32_t taps;
+  const int16_t* coeff;       /* host, [p][taps] */
+  const int32_t* phase_start; /* host, [p], or NULL for the default */
+} aol_polyphase;
+
+/* Default window starts for (p, q, taps) into out[0..p). AOL_ERR_INVALID if
+ * any argument is < 1 or out is NULL. */
+aol_status aol_default_phase_starts(int32_t p, int32_t q, int32_t taps, int32_t* out);
+
+/* Output size of a h x w plane: out_h = vf.p*ceil(h/vf.q), out_w =
+ * hf.p*ceil(w/hf.q). The only way callers learn output sizes. */
+aol_status aol_downscale_output_shape(int64_t h, int64_t w, const aol_polyphase* hf,
+                                      const aol_polyphase* vf, int64_t* out_h, int64_t* out_w);
+
+/* --------------------------------------------------------------------------
+ * Frame downscaler plans (Sec. III: horizontal filter then vertical filter,
+ * repeated for every frame and every colour plane; the two filters are fused
+ * in one kernel and the intermediate frame never leaves the chip).
+ *
+ * One plan covers up to AOL_MAX_PLANES planes (e.g. Y, U, V of I420), all
+ * filtered with the same hf (along each line) and vf (along each column).
+ * Pitches are in elements of the plane's type (uint8 for AOL_PREC_U8; 16-bit
+ * for the float input; float32 for the float output); 0 means tightly
+ * packed. The integer path rounds the intermediate to uint8 after the
+ * horizontal pass, exactly as two separate filters exchanging a uint8 frame.
+ * ------------------------------------------------------------------------ */
+typedef struct aol_plane_desc {
+  int64_t height;
+  int64_t width;
+  int64_t in_pitch;  /* elements between input rows, >= width, or 0 */
+  int64_t out_pitch; /* elements between output rows, >= output width, or 0 */
+} aol_plane_desc;
+
+typedef struct aol_plan aol_plan;
+
+/* Validate shapes and filters, build the device tables. AOL_ERR_UNSUPPORTED
+ * for p > AOL_MAX_P, q > AOL_MAX_Q, taps > AOL_MAX_TAPS, |coeff| >
+ * AOL_MAX_COEFF (U8), coefficients whose c/256 is not exact in the chosen
+ * float format (BF16: at most 8 significant bits), or planes whose height or
+ * width exceeds 2^30. */
+aol_status aol_downscale_plan_create(const aol_plane_desc* planes, int32_t n_planes,
+                                     const aol_polyphase* hf, const aol_polyphase* vf,
+                                     aol_precision prec, aol_plan** out);
+aol_status aol_plan_destroy(aol_plan* plan);
+
+/* Tile shape of a plan in repetitions (tile_rx along lines, tile_ry along
+ * columns). tile_rx*hf.q must be a multiple of 16 elements (U8) or 8
+ * (float); at most 512 outputs per tile and axis. AOL_ERR_INVALID for a
+ * misaligned tile, AOL_ERR_UNSUPPORTED if it would not fit the chip's shared
+ * memory. Optional: plans start with about 128 input pixels per tile side. */
+aol_status aol_plan_set_tile(aol_plan* plan, int32_t tile_rx, int32_t tile_ry);
+
+/* Integer path (plan precision AOL_PREC_U8). For plane j, d_in[j] points to
+ * frame 0 of n_frames frames spaced in_frame_stride[j] elements apart, and
+ * d_out[j] to the outputs spaced out_frame_stride[j] apart. Host arrays of
+ * length n_planes. Vector loads need 16-byte aligned rows and 4-byte aligned
+ * output rows; other layouts take a slower element-wise path. */
+aol_status aol_downscale_u8(aol_plan* plan, int32_t n_frames, const uint8_t* const* d_in,
+                            const int64_t* in_frame_stride, uint8_t* const* d_out,
+                            const int64_t* out_frame_stride, hipStream_t stream);
+
+/* Float path (AOL_PREC_BF16 / AOL_PREC_FP16): inputs are 16-bit bit patterns
+ * of normalised pixels, outputs float32, weights coeff/256 applied on the
+ * matrix cores with float32 accumulation; the intermediate is kept on chip
+ * as a hi/lo pair of 16-bit values. */
+aol_status aol_downscale_f(aol_plan* plan, int32_t n_frames, const void* const* d_in,
+                           const int64_t* in_frame_stride, float* const* d_out,
+                           const int64_t* out_frame_stride, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AOLMI_H */

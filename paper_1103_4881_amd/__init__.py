@@ -1,0 +1,249 @@
+"""Python binding of ``libaolmi.so``: Array-OL repetitive tasks on MI355X.
+
+A thin ctypes layer over the C ABI declared in ``include/aolmi.h``. Functions
+named ``aol_*`` mirror the C entry points one to one (argument marshalling
+only); ``DownscalePlan`` and ``WeightedSumPlan`` wrap them for torch tensors.
+PyTorch is used only for device memory and streams: tensors are passed as
+``data_ptr()`` and ``torch.cuda.current_stream().cuda_stream``; every step
+of the computation runs in the library's HIP kernels.
+
+The library must be built (``python -m paper_1103_4881_amd.build``); when it
+is missing, importing this package raises ``ImportError``. There is no CPU
+fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaolmi.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1103_4881_amd.build`")
+
+# torch carries its own HIP runtime under the same soname as ROCm's
+# (libamdhip64.so.7). Loading torch first makes the library bind to that one
+# runtime, so torch's streams and allocations are valid handles for it.
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+AOL_OK = 0
+AOL_ERR_INVALID = -1
+AOL_ERR_UNSUPPORTED = -2
+AOL_ERR_NOMEM = -3
+AOL_ERR_HIP = -4
+
+AOL_PREC_U8 = 0
+AOL_PREC_BF16 = 1
+AOL_PREC_FP16 = 2
+_PREC = {"u8": AOL_PREC_U8, "bf16": AOL_PREC_BF16, "fp16": AOL_PREC_FP16}
+
+AOL_MAX_RANK = 4
+
+
+class AolError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"aol status {status}: {msg}")
+        self.status = status
+        self.msg = msg
+
+
+c_i32p = ctypes.POINTER(ctypes.c_int32)
+c_i64p = ctypes.POINTER(ctypes.c_int64)
+c_i16p = ctypes.POINTER(ctypes.c_int16)
+
+
+class aol_polyphase(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("q", ctypes.c_int32), ("taps", ctypes.c_int32),
+                ("coeff", c_i16p), ("phase_start", c_i32p)]
+
+
+class aol_plane_desc(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_int64), ("width", ctypes.c_int64),
+                ("in_pitch", ctypes.c_int64), ("out_pitch", ctypes.c_int64)]
+
+
+def _proto(name, restype, *args):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = list(args)
+    return f
+
+
+_lib.aol_last_error.restype = ctypes.c_char_p
+_lib.aol_version.restype = ctypes.c_char_p
+_proto("aol_default_phase_starts", ctypes.c_int, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, c_i32p)
+_proto("aol_downscale_output_shape", ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+       ctypes.POINTER(aol_polyphase), ctypes.POINTER(aol_polyphase), c_i64p, c_i64p)
+_proto("aol_downscale_plan_create", ctypes.c_int, ctypes.POINTER(aol_plane_desc), ctypes.c_int32,
+       ctypes.POINTER(aol_polyphase), ctypes.POINTER(aol_polyphase), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p))
+_proto("aol_plan_destroy", ctypes.c_int, ctypes.c_void_p)
+_proto("aol_plan_set_tile", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32)
+_proto("aol_downscale_u8", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), c_i64p,
+       ctypes.POINTER(ctypes.c_void_p), c_i64p, ctypes.c_void_p)
+_proto("aol_downscale_f", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), c_i64p,
+       ctypes.POINTER(ctypes.c_void_p), c_i64p, ctypes.c_void_p)
+
+
+def _check(status: int):
+    if status != AOL_OK:
+        raise AolError(status, _lib.aol_last_error().decode())
+
+
+def aol_last_error() -> str:
+    return _lib.aol_last_error().decode()
+
+
+def aol_version() -> str:
+    return _lib.aol_version().decode()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# --------------------------------------------------------------------------
+# filters
+# --------------------------------------------------------------------------
+
+class Polyphase:
+    """One axis' filter: ratio p/q, integer taps ``coeff[p][taps]``, optional window starts."""
+
+    def __init__(self, p: int, q: int, coeff, phase_start=None):
+        self.coeff = np.ascontiguousarray(np.asarray(coeff, dtype=np.int16).reshape(int(p), -1))
+        self.p, self.q, self.taps = int(p), int(q), int(self.coeff.shape[1])
+        self.phase_start = None if phase_start is None else np.ascontiguousarray(np.asarray(phase_start, np.int32))
+        self._c = aol_polyphase(self.p, self.q, self.taps, self.coeff.ctypes.data_as(c_i16p),
+                                None if self.phase_start is None else self.phase_start.ctypes.data_as(c_i32p))
+
+    @property
+    def c_struct(self) -> aol_polyphase:
+        return self._c
+
+
+def aol_default_phase_starts(p: int, q: int, taps: int) -> list:
+    out = (ctypes.c_int32 * int(p))()
+    _check(_lib.aol_default_phase_starts(p, q, taps, out))
+    return list(out)
+
+
+def aol_downscale_output_shape(h: int, w: int, hf: Polyphase, vf: Polyphase):
+    oh, ow = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.aol_downscale_output_shape(h, w, ctypes.byref(hf.c_struct), ctypes.byref(vf.c_struct),
+                                           ctypes.byref(oh), ctypes.byref(ow)))
+    return oh.value, ow.value
+
+
+# --------------------------------------------------------------------------
+# frame downscaler
+# --------------------------------------------------------------------------
+
+def aol_downscale_plan_create(planes, hf: Polyphase, vf: Polyphase, precision="u8"):
+    """``planes``: list of (height, width[, in_pitch, out_pitch]). Returns an opaque handle."""
+    arr = (aol_plane_desc * len(planes))()
+    for i, d in enumerate(planes):
+        d = [int(v) for v in d] + [0] * (4 - len(d))
+        arr[i] = aol_plane_desc(*d[:4])
+    h = ctypes.c_void_p()
+    prec = _PREC[precision] if isinstance(precision, str) else int(precision)
+    _check(_lib.aol_downscale_plan_create(arr, len(planes), ctypes.byref(hf.c_struct), ctypes.byref(vf.c_struct),
+                                          prec, ctypes.byref(h)))
+    return h
+
+
+def aol_plan_destroy(plan):
+    _check(_lib.aol_plan_destroy(plan))
+
+
+def aol_plan_set_tile(plan, tile_rx: int, tile_ry: int):
+    _check(_lib.aol_plan_set_tile(plan, tile_rx, tile_ry))
+
+
+def _ptrs(vals):
+    return (ctypes.c_void_p * len(vals))(*[int(v) for v in vals])
+
+
+def _i64s(vals):
+    return (ctypes.c_int64 * len(vals))(*[int(v) for v in vals])
+
+
+def aol_downscale_u8(plan, n_frames, d_in, in_frame_stride, d_out, out_frame_stride, stream=None):
+    _check(_lib.aol_downscale_u8(plan, int(n_frames), _ptrs(d_in), _i64s(in_frame_stride), _ptrs(d_out),
+                                 _i64s(out_frame_stride), _stream_handle(stream)))
+
+
+def aol_downscale_f(plan, n_frames, d_in, in_frame_stride, d_out, out_frame_stride, stream=None):
+    _check(_lib.aol_downscale_f(plan, int(n_frames), _ptrs(d_in), _i64s(in_frame_stride), _ptrs(d_out),
+                                _i64s(out_frame_stride), _stream_handle(stream)))
+
+
+class DownscalePlan:
+    """Plan for a set of planes filtered by (hf, vf); runs on torch device tensors.
+
+    Each plane's frames are a tensor ``[n_frames, h, w]`` (uint8 for ``"u8"``;
+    int16/uint16/bfloat16/float16 bit patterns for ``"bf16"``/``"fp16"``) with
+    unit stride along rows; outputs are ``[n_frames, out_h, out_w]`` uint8 or
+    float32 tensors with unit stride along rows.
+    """
+
+    def __init__(self, shapes, hf: Polyphase, vf: Polyphase, precision="u8", in_pitches=None, out_pitches=None):
+        self.hf, self.vf, self.precision = hf, vf, precision
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.out_shapes = [aol_downscale_output_shape(h, w, hf, vf) for (h, w) in self.shapes]
+        self.in_pitches = list(in_pitches or [w for (h, w) in self.shapes])
+        self.out_pitches = list(out_pitches or [ow for (oh, ow) in self.out_shapes])
+        self._h = aol_downscale_plan_create(
+            [(h, w, self.in_pitches[i], self.out_pitches[i]) for i, (h, w) in enumerate(self.shapes)],
+            hf, vf, precision)
+
+    def set_tile(self, tile_rx: int, tile_ry: int):
+        aol_plan_set_tile(self._h, tile_rx, tile_ry)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            aol_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_tensors(self, ins, outs):
+        import torch
+        if len(ins) != len(self.shapes) or len(outs) != len(self.shapes):
+            raise ValueError("one input and one output tensor per plane")
+        n = ins[0].shape[0]
+        for i, (t, (h, w), o, (oh, ow)) in enumerate(zip(ins, self.shapes, outs, self.out_shapes)):
+            if not (t.is_cuda and o.is_cuda):
+                raise ValueError("tensors must be on the GPU")
+            if t.stride(1) != self.in_pitches[i] or o.stride(1) != self.out_pitches[i]:
+                raise ValueError("row strides must equal the plan's pitches")
+            if t.dim() != 3 or t.shape[0] != n or t.shape[1] != h or t.shape[2] != w or t.stride(2) != 1:
+                raise ValueError(f"input must be [n_frames, {h}, {w}] with unit column stride")
+            if o.dim() != 3 or o.shape[0] != n or o.shape[1] != oh or o.shape[2] != ow or o.stride(2) != 1:
+                raise ValueError(f"output must be [n_frames, {oh}, {ow}] with unit column stride")
+            if self.precision == "u8":
+                if t.dtype != torch.uint8 or o.dtype != torch.uint8:
+                    raise ValueError("u8 plans take uint8 tensors")
+            else:
+                if t.element_size() != 2 or o.dtype != torch.float32:
+                    raise ValueError("float plans take 16-bit inputs and float32 outputs")
+        return n
+
+    def run(self, ins, outs, stream=None):
+        n = self._check_tensors(ins, outs)
+        fn = aol_downscale_u8 if self.precision == "u8" else aol_downscale_f
+        fn(self._h, n, [t.data_ptr() for t in ins], [t.stride(0) for t in ins],
+           [o.data_ptr() for o in outs], [o.stride(0) for o in outs], stream)

@@ -1,0 +1,460 @@
+// Host side of the downscaler: validation, per-axis band tables, plans and
+// the C ABI entry points declared in include/aolmi.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "aol_internal.h"
+#include "aolmi.h"
+#include "common.h"
+
+namespace aol {
+
+hipError_t fused_prepare(int elem, size_t lds_bytes);
+hipError_t fused_launch(int elem, const FusedArgs& a, size_t lds_bytes, hipStream_t stream);
+
+static thread_local std::string g_err;
+
+aol_status fail(aol_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+aol_status ok() {
+  g_err.clear();
+  return AOL_OK;
+}
+
+aol_status hip_fail(hipError_t e, const char* what) {
+  return fail(AOL_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+const char* last_error() { return g_err.c_str(); }
+
+static int64_t floor_div(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return q;
+}
+
+static int64_t pmod64(int64_t a, int64_t m) {
+  int64_t r = a % m;
+  return r < 0 ? r + m : r;
+}
+
+void default_starts(int p, int q, int taps, int32_t* out) {
+  // The output pixel of phase phi is centred at input coordinate
+  // ((2phi+1)q - p) / (2p) (pixel centres at integer positions); the window
+  // of `taps` pixels starts floor((taps-1)/2) before the pixel under it.
+  for (int phi = 0; phi < p; ++phi)
+    out[phi] = (int32_t)(floor_div((int64_t)(2 * phi + 1) * q - p, 2LL * p) - (taps - 1) / 2);
+}
+
+aol_status check_filter(const aol_polyphase* f, const char* name, FilterHost& out) {
+  if (!f) return fail(AOL_ERR_INVALID, "%s: NULL filter", name);
+  if (f->p < 1 || f->q < 1 || f->taps < 1) return fail(AOL_ERR_INVALID, "%s: p, q and taps must be >= 1", name);
+  if (!f->coeff) return fail(AOL_ERR_INVALID, "%s: NULL coefficients", name);
+  if (f->p > AOL_MAX_P) return fail(AOL_ERR_UNSUPPORTED, "%s: p=%d exceeds %d", name, f->p, AOL_MAX_P);
+  if (f->q > AOL_MAX_Q) return fail(AOL_ERR_UNSUPPORTED, "%s: q=%d exceeds %d", name, f->q, AOL_MAX_Q);
+  if (f->taps > AOL_MAX_TAPS) return fail(AOL_ERR_UNSUPPORTED, "%s: taps=%d exceeds %d", name, f->taps, AOL_MAX_TAPS);
+  out.p = f->p;
+  out.q = f->q;
+  out.taps = f->taps;
+  out.c.assign(f->coeff, f->coeff + (size_t)f->p * f->taps);
+  out.s.resize(f->p);
+  if (f->phase_start) {
+    for (int i = 0; i < f->p; ++i) {
+      if (f->phase_start[i] < -4096 || f->phase_start[i] > 4096)
+        return fail(AOL_ERR_UNSUPPORTED, "%s: phase_start[%d]=%d outside [-4096, 4096]", name, i, f->phase_start[i]);
+      out.s[i] = f->phase_start[i];
+    }
+  } else {
+    default_starts(f->p, f->q, f->taps, out.s.data());
+  }
+  return AOL_OK;
+}
+
+static uint16_t f32_to_bf16_exact(float x, bool* exact) {
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  *exact = (u & 0xFFFFu) == 0;
+  return (uint16_t)(u >> 16);
+}
+
+static uint16_t f32_to_f16_exact(float x, bool* exact) {
+  // Exact conversion for the values used here (c/256 with |c| <= 2047):
+  // normal fp16 covers 2^-14 .. 65504 with 11 significant bits.
+  _Float16 h = (_Float16)x;
+  *exact = ((float)h == x);
+  uint16_t r;
+  memcpy(&r, &h, 2);
+  return r;
+}
+
+aol_status build_band(const FilterHost& f, int tr, int elem, bool h_axis, AxisBand& band,
+                      std::vector<uint8_t>& frags, const char* name) {
+  memset(&band, 0, sizeof band);
+  const int E = elem == kU8 ? 16 : 8;
+  const int p = f.p, q = f.q, T = f.taps;
+  int s_min = INT_MAX, s_end = INT_MIN;
+  for (int phi = 0; phi < p; ++phi) {
+    s_min = std::min(s_min, f.s[phi]);
+    s_end = std::max(s_end, f.s[phi] + T);
+  }
+  band.p = p;
+  band.q = q;
+  band.taps = T;
+  band.tr = tr;
+  band.n_out = p * tr;
+  band.nblk = (band.n_out + 15) / 16;
+  band.span = s_end - s_min;
+  band.s_min = s_min;
+  band.delta = h_axis ? (int)pmod64(s_min, E) : 0;
+  band.chunk_elems = E;
+  if (band.nblk > kMaxNB) return fail(AOL_ERR_UNSUPPORTED, "%s: %d outputs per tile exceed %d", name, band.n_out, kMaxNB * 16);
+  if (h_axis && (q * tr) % E != 0) return fail(AOL_ERR_INVALID, "%s: q*tile must be a multiple of %d", name, E);
+
+  bool split = false;
+  if (elem == kU8) {
+    for (int v : f.c) {
+      if (v < -AOL_MAX_COEFF || v > AOL_MAX_COEFF)
+        return fail(AOL_ERR_UNSUPPORTED, "%s: coefficient %d outside +-%d", name, v, AOL_MAX_COEFF);
+      if (v < -128 || v > 127) split = true;
+    }
+  } else {
+    for (int v : f.c) {
+      bool exact = false;
+      if (elem == kBF16) f32_to_bf16_exact((float)v / 256.0f, &exact);
+      else f32_to_f16_exact((float)v / 256.0f, &exact);
+      if (v < -AOL_MAX_COEFF || v > AOL_MAX_COEFF || !exact)
+        return fail(AOL_ERR_UNSUPPORTED, "%s: coefficient %d/256 is not exact in the %s format", name, v,
+                    elem == kBF16 ? "bf16" : "fp16");
+    }
+  }
+  band.split = split ? 1 : 0;
+
+  // Per output block: the window of tile-local element positions (position 0
+  // is the start of the tile's first chunk) its outputs read.
+  int nfrag = 0;
+  int chunk_hi = 0;
+  frags.clear();
+  for (int b = 0; b < band.nblk; ++b) {
+    int lo = INT_MAX, hi = INT_MIN;
+    for (int o = 16 * b; o < std::min(16 * b + 16, band.n_out); ++o) {
+      const int r = o / p, phi = o % p;
+      const int st = band.delta + q * r + f.s[phi] - s_min;
+      lo = std::min(lo, st);
+      hi = std::max(hi, st + T);
+    }
+    const int c0 = lo / E;
+    const int c1 = (hi + E - 1) / E;
+    const int nk = (c1 - c0 + 3) / 4;
+    band.chunk0[b] = c0;
+    band.nk[b] = nk;
+    band.frag[b] = nfrag;
+    chunk_hi = std::max(chunk_hi, c0 + 4 * nk);
+    for (int kb = 0; kb < nk; ++kb) {
+      const int parts = split ? 2 : 1;
+      const size_t base = frags.size();
+      frags.resize(base + (size_t)parts * kLanes * 16, 0);
+      for (int lane = 0; lane < kLanes; ++lane) {
+        const int g = lane >> 4, nn = lane & 15;
+        const int o = 16 * b + nn;
+        for (int e = 0; e < E; ++e) {
+          const int k = (c0 + 4 * kb + g) * E + e;
+          int c = 0;
+          if (o < band.n_out) {
+            const int r = o / p, phi = o % p;
+            const int t = k - (band.delta + q * r + f.s[phi] - s_min);
+            if (t >= 0 && t < T) c = f.c[(size_t)phi * T + t];
+          }
+          if (elem == kU8) {
+            const int lo7 = (int)pmod64(c + 64, 128) - 64;  // c = lo7 + 128*hi
+            const int hi7 = (c - lo7) / 128;
+            frags[base + (size_t)lane * 16 + e] = (uint8_t)(int8_t)(split ? lo7 : c);
+            if (split) frags[base + (size_t)kLanes * 16 + (size_t)lane * 16 + e] = (uint8_t)(int8_t)hi7;
+          } else {
+            bool exact;
+            const uint16_t bits = elem == kBF16 ? f32_to_bf16_exact((float)c / 256.0f, &exact)
+                                                : f32_to_f16_exact((float)c / 256.0f, &exact);
+            memcpy(&frags[base + (size_t)lane * 16 + 2 * e], &bits, 2);
+          }
+        }
+      }
+      nfrag += 1;
+    }
+    for (int nn = 0; nn < 16; ++nn) {
+      const int o = 16 * b + nn;
+      int64_t S = 0;
+      if (o < band.n_out) {
+        const int phi = o % p;
+        for (int t = 0; t < T; ++t) S += f.c[(size_t)phi * T + t];
+      }
+      band.bias[b * 16 + nn] = (int32_t)(128 * S + 128);
+    }
+  }
+  band.nchunks = chunk_hi;
+  return AOL_OK;
+}
+
+}  // namespace aol
+
+using namespace aol;
+
+struct aol_plan {
+  int n_planes = 0;
+  aol_plane_desc planes[kMaxPlanes];
+  int64_t mh[kMaxPlanes], mw[kMaxPlanes];
+  int elem = kU8;
+  FilterHost hf, vf;
+  int trx = 16, try_ = 16;
+  AxisBand hb{}, vb{};
+  int zpitch = 0, zrows = 0, zmb = 0;
+  size_t lds = 0;
+  DeviceBuf d_hb, d_vb, d_hfrag, d_vfrag;
+};
+
+static int gcd_int(int a, int b) {
+  while (b) {
+    const int t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// Repetitions per tile along one axis: about 128 input elements, a whole
+// number of 16-byte chunks along lines, at most kMaxNB*16 outputs.
+static int tile_align(const FilterHost& f, int elem, bool h_axis) {
+  const int E = elem == kU8 ? 16 : 8;
+  return h_axis ? E / gcd_int(f.q, E) : 1;
+}
+
+static int default_tile(const FilterHost& f, int elem, bool h_axis) {
+  const int al = tile_align(f, elem, h_axis);
+  int tr = (128 + f.q - 1) / f.q;
+  tr = (tr + al - 1) / al * al;
+  const int cap = std::max(al, (kMaxNB * 16 / f.p) / al * al);
+  return std::min(tr, cap);
+}
+
+static aol_status plan_build_tables(aol_plan* pl, int trx, int try_) {
+  AxisBand hb, vb;
+  std::vector<uint8_t> hfr, vfr;
+  aol_status st = build_band(pl->hf, trx, pl->elem, true, hb, hfr, "hf");
+  if (st) return st;
+  st = build_band(pl->vf, try_, pl->elem, false, vb, vfr, "vf");
+  if (st) return st;
+  const int E = pl->elem == kU8 ? 16 : 8;
+  const int es = pl->elem == kU8 ? 1 : 2;
+  // Intermediate lines the vertical pass may read (all K-steps of a full tile).
+  const int zlines = ((vb.nchunks * E) + 15) / 16 * 16;
+  int zpitch = zlines;
+  if (((zpitch * es) / 16) % 2 == 0) zpitch += 16 / es;  // odd multiple of 16 bytes between LDS rows
+  const int zrows = hb.nblk * 16;
+  const size_t lds = (size_t)zrows * zpitch * es * (pl->elem == kU8 ? 1 : 2);
+  if (lds > 160 * 1024) return fail(AOL_ERR_UNSUPPORTED, "tile %dx%d needs %zu bytes of LDS", trx, try_, lds);
+  hipError_t e = fused_prepare(pl->elem, lds);
+  if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+  DeviceBuf dhb, dvb, dhf, dvf;
+  if ((st = dhb.upload(&hb, sizeof hb))) return st;
+  if ((st = dvb.upload(&vb, sizeof vb))) return st;
+  if ((st = dhf.upload(hfr.data(), hfr.size()))) return st;
+  if ((st = dvf.upload(vfr.data(), vfr.size()))) return st;
+  pl->hb = hb;
+  pl->vb = vb;
+  pl->trx = trx;
+  pl->try_ = try_;
+  pl->zpitch = zpitch;
+  pl->zrows = zrows;
+  pl->zmb = zlines / 16;
+  pl->lds = lds;
+  pl->d_hb = std::move(dhb);
+  pl->d_vb = std::move(dvb);
+  pl->d_hfrag = std::move(dhf);
+  pl->d_vfrag = std::move(dvf);
+  return AOL_OK;
+}
+
+extern "C" {
+
+const char* aol_last_error(void) { return last_error(); }
+
+const char* aol_version(void) { return "0.1.0"; }
+
+aol_status aol_default_phase_starts(int32_t p, int32_t q, int32_t taps, int32_t* out) {
+  if (p < 1 || q < 1 || taps < 1 || !out) return fail(AOL_ERR_INVALID, "p, q, taps must be >= 1 and out non-NULL");
+  default_starts(p, q, taps, out);
+  return ok();
+}
+
+aol_status aol_downscale_output_shape(int64_t h, int64_t w, const aol_polyphase* hf, const aol_polyphase* vf,
+                                      int64_t* out_h, int64_t* out_w) {
+  if (!hf || !vf || !out_h || !out_w) return fail(AOL_ERR_INVALID, "NULL argument");
+  if (h < 1 || w < 1) return fail(AOL_ERR_INVALID, "plane size must be >= 1");
+  if (hf->p < 1 || hf->q < 1 || vf->p < 1 || vf->q < 1) return fail(AOL_ERR_INVALID, "p and q must be >= 1");
+  *out_h = (int64_t)vf->p * ((h + vf->q - 1) / vf->q);
+  *out_w = (int64_t)hf->p * ((w + hf->q - 1) / hf->q);
+  return ok();
+}
+
+aol_status aol_downscale_plan_create(const aol_plane_desc* planes, int32_t n_planes, const aol_polyphase* hf,
+                                     const aol_polyphase* vf, aol_precision prec, aol_plan** out) {
+  if (!out) return fail(AOL_ERR_INVALID, "NULL plan output");
+  *out = nullptr;
+  if (!planes || n_planes < 1) return fail(AOL_ERR_INVALID, "need at least one plane");
+  if (n_planes > AOL_MAX_PLANES) return fail(AOL_ERR_UNSUPPORTED, "at most %d planes", AOL_MAX_PLANES);
+  if (prec != AOL_PREC_U8 && prec != AOL_PREC_BF16 && prec != AOL_PREC_FP16)
+    return fail(AOL_ERR_INVALID, "unknown precision %d", (int)prec);
+  aol_plan* pl = new (std::nothrow) aol_plan();
+  if (!pl) return fail(AOL_ERR_NOMEM, "plan allocation");
+  pl->elem = prec == AOL_PREC_U8 ? kU8 : prec == AOL_PREC_BF16 ? kBF16 : kFP16;
+  aol_status st = check_filter(hf, "hf", pl->hf);
+  if (!st) st = check_filter(vf, "vf", pl->vf);
+  if (st) {
+    delete pl;
+    return st;
+  }
+  pl->n_planes = n_planes;
+  for (int i = 0; i < n_planes; ++i) {
+    aol_plane_desc d = planes[i];
+    if (d.height < 1 || d.width < 1) {
+      delete pl;
+      return fail(AOL_ERR_INVALID, "plane %d: size %lldx%lld", i, (long long)d.height, (long long)d.width);
+    }
+    if (d.height > (1LL << 30) || d.width > (1LL << 30)) {
+      delete pl;
+      return fail(AOL_ERR_UNSUPPORTED, "plane %d: sides above 2^30", i);
+    }
+    int64_t mh = (int64_t)pl->vf.p * ((d.height + pl->vf.q - 1) / pl->vf.q);
+    int64_t mw = (int64_t)pl->hf.p * ((d.width + pl->hf.q - 1) / pl->hf.q);
+    if (d.in_pitch == 0) d.in_pitch = d.width;
+    if (d.out_pitch == 0) d.out_pitch = mw;
+    if (d.in_pitch < d.width || d.out_pitch < mw) {
+      delete pl;
+      return fail(AOL_ERR_INVALID, "plane %d: pitch smaller than the row", i);
+    }
+    if (mh > (1LL << 30) || mw > (1LL << 30)) {
+      delete pl;
+      return fail(AOL_ERR_UNSUPPORTED, "plane %d: output sides above 2^30", i);
+    }
+    pl->planes[i] = d;
+    pl->mh[i] = mh;
+    pl->mw[i] = mw;
+  }
+  st = plan_build_tables(pl, default_tile(pl->hf, pl->elem, true), default_tile(pl->vf, pl->elem, false));
+  if (st) {
+    delete pl;
+    return st;
+  }
+  *out = pl;
+  return ok();
+}
+
+aol_status aol_plan_destroy(aol_plan* plan) {
+  delete plan;
+  return ok();
+}
+
+aol_status aol_plan_set_tile(aol_plan* plan, int32_t tile_rx, int32_t tile_ry) {
+  if (!plan) return fail(AOL_ERR_INVALID, "NULL plan");
+  if (tile_rx < 1 || tile_ry < 1) return fail(AOL_ERR_INVALID, "tile repetitions must be >= 1");
+  const int al = tile_align(plan->hf, plan->elem, true);
+  if (tile_rx % al)
+    return fail(AOL_ERR_INVALID, "tile_rx*q must cover whole 16-byte chunks (tile_rx multiple of %d)", al);
+  if (tile_rx * plan->hf.p > kMaxNB * 16 || tile_ry * plan->vf.p > kMaxNB * 16)
+    return fail(AOL_ERR_UNSUPPORTED, "more than %d outputs per tile", kMaxNB * 16);
+  aol_status st = plan_build_tables(plan, tile_rx, tile_ry);
+  if (st) return st;
+  return ok();
+}
+
+}  // extern "C"
+
+static aol_status run_fused(aol_plan* plan, int32_t n_frames, const void* const* d_in, const int64_t* in_fs,
+                            void* const* d_out, const int64_t* out_fs, hipStream_t stream, int out_es) {
+  if (n_frames < 0) return fail(AOL_ERR_INVALID, "n_frames < 0");
+  if (n_frames == 0) return ok();
+  if (!d_in || !d_out || !in_fs || !out_fs) return fail(AOL_ERR_INVALID, "NULL pointer array");
+  const int in_es = plan->elem == kU8 ? 1 : 2;
+  FusedArgs a;
+  memset(&a, 0, sizeof a);
+  int64_t tiles = 0;
+  for (int i = 0; i < plan->n_planes; ++i) {
+    const aol_plane_desc& d = plan->planes[i];
+    if (!d_in[i] || !d_out[i]) return fail(AOL_ERR_INVALID, "plane %d: NULL buffer", i);
+    if (n_frames > 1 && (in_fs[i] < d.in_pitch * (d.height - 1) + d.width || out_fs[i] < d.out_pitch * (plan->mh[i] - 1) + plan->mw[i]))
+      return fail(AOL_ERR_INVALID, "plane %d: frame stride smaller than a frame", i);
+    if ((uintptr_t)d_in[i] % in_es || (uintptr_t)d_out[i] % out_es)
+      return fail(AOL_ERR_INVALID, "plane %d: buffer not aligned to its element size", i);
+    PlaneArg& p = a.pl[i];
+    p.in = d_in[i];
+    p.out = d_out[i];
+    p.in_pitch = d.in_pitch;
+    p.out_pitch = d.out_pitch;
+    p.in_fstride = in_fs[i];
+    p.out_fstride = out_fs[i];
+    p.h = (int32_t)d.height;
+    p.w = (int32_t)d.width;
+    p.mh = (int32_t)plan->mh[i];
+    p.mw = (int32_t)plan->mw[i];
+    p.rx = (int32_t)((d.width + plan->hf.q - 1) / plan->hf.q);
+    p.ry = (int32_t)((d.height + plan->vf.q - 1) / plan->vf.q);
+    p.tiles_x = (p.rx + plan->trx - 1) / plan->trx;
+    p.tiles_y = (p.ry + plan->try_ - 1) / plan->try_;
+    p.tile_base = (int32_t)tiles;
+    tiles += (int64_t)p.tiles_x * p.tiles_y;
+    const int64_t ein = 16 / in_es;
+    p.vec_in = ((uintptr_t)d_in[i] % 16 == 0) && (d.in_pitch % ein == 0) && (n_frames == 1 || in_fs[i] % ein == 0);
+    // each lane stores four consecutive outputs of one row at once
+    p.vec_out = ((uintptr_t)d_out[i] % (4 * out_es) == 0) && (d.out_pitch % 4 == 0) &&
+                (n_frames == 1 || out_fs[i] % 4 == 0) && ((plan->hf.p * plan->trx) % 4 == 0);
+  }
+  const int64_t total = tiles * n_frames;
+  if (total > INT_MAX || tiles > INT_MAX) return fail(AOL_ERR_UNSUPPORTED, "too many tiles in one launch");
+  a.n_planes = plan->n_planes;
+  a.n_frames = n_frames;
+  a.tiles_per_frame = (int32_t)tiles;
+  a.total_tiles = (int32_t)total;
+  a.hb = (const AxisBand*)plan->d_hb.ptr;
+  a.vb = (const AxisBand*)plan->d_vb.ptr;
+  a.hfrag = plan->d_hfrag.ptr;
+  a.vfrag = plan->d_vfrag.ptr;
+  a.zpitch = plan->zpitch;
+  a.zrows = plan->zrows;
+  a.z_mblocks = plan->zmb;
+  hipError_t e = fused_launch(plan->elem, a, plan->lds, stream);
+  if (e != hipSuccess) return hip_fail(e, "fused kernel launch");
+  return ok();
+}
+
+extern "C" {
+
+aol_status aol_downscale_u8(aol_plan* plan, int32_t n_frames, const uint8_t* const* d_in,
+                            const int64_t* in_frame_stride, uint8_t* const* d_out, const int64_t* out_frame_stride,
+                            hipStream_t stream) {
+  if (!plan) return fail(AOL_ERR_INVALID, "NULL plan");
+  if (plan->elem != kU8) return fail(AOL_ERR_INVALID, "plan precision is not AOL_PREC_U8");
+  return run_fused(plan, n_frames, (const void* const*)d_in, in_frame_stride, (void* const*)d_out, out_frame_stride,
+                   stream, 1);
+}
+
+aol_status aol_downscale_f(aol_plan* plan, int32_t n_frames, const void* const* d_in, const int64_t* in_frame_stride,
+                           float* const* d_out, const int64_t* out_frame_stride, hipStream_t stream) {
+  if (!plan) return fail(AOL_ERR_INVALID, "NULL plan");
+  if (plan->elem == kU8) return fail(AOL_ERR_INVALID, "plan precision is AOL_PREC_U8; use aol_downscale_u8");
+  return run_fused(plan, n_frames, d_in, in_frame_stride, (void* const*)d_out, out_frame_stride, stream, 4);
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+"""GPU parity of the fused downscaler against the CPU oracle.
+
+Integer path: bit-exact. Float path: max-abs error against the float64
+oracle evaluated on the identical bf16/fp16 inputs, within 1e-3 normalised
+pixels (the kernel keeps a hi/lo intermediate and float32 accumulation, so
+the observed error is around 1e-6; the bound is the stated tolerance).
+"""
+
+import numpy as np
+import pytest
+
+import synthgen
+from oracle import polyphase as pp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+aol = pytest.importorskip("paper_1103_4881_amd")
+
+FLOAT_TOL = 1e-3
+
+
+def _filters(p, q, T, kind="design", seed=0, starts=None):
+    if kind == "design":
+        c = synthgen.design_taps(p, q, T)
+    else:
+        g = synthgen.rng_for(seed, 5)
+        c = g.integers(-300, 400, size=(p, T))
+        c[:, 0] += 256 - c.sum(axis=1)
+        c = np.clip(c, -2047, 2047)
+    return aol.Polyphase(p, q, c, starts), pp.Filter(p, q, c, starts)
+
+
+def _run_u8(planes_np, hf, vf, tile=None, in_pitch_pad=0, out_pitch_pad=0):
+    """planes_np: list of uint8 arrays [F, H, W]. Returns list of uint8 [F, MH, MW]."""
+    shapes = [a.shape[1:] for a in planes_np]
+    out_shapes = [aol.aol_downscale_output_shape(h, w, hf, vf) for (h, w) in shapes]
+    ins, outs, ip, op = [], [], [], []
+    for a, (oh, ow) in zip(planes_np, out_shapes):
+        F, H, W = a.shape
+        buf = torch.full((F, H, W + in_pitch_pad), 77, dtype=torch.uint8, device="cuda")
+        buf[:, :, :W] = torch.from_numpy(a).cuda()
+        ins.append(buf[:, :, :W])
+        ip.append(W + in_pitch_pad)
+        ob = torch.full((F, oh, ow + out_pitch_pad), 0xA5, dtype=torch.uint8, device="cuda")
+        outs.append(ob)
+        op.append(ow + out_pitch_pad)
+    plan = aol.DownscalePlan(shapes, hf, vf, "u8", in_pitches=ip, out_pitches=op)
+    if tile:
+        plan.set_tile(*tile)
+    plan.run(ins, [o[:, :, :s[1]] for o, s in zip(outs, out_shapes)])
+    torch.cuda.synchronize()
+    res = []
+    for o, (oh, ow) in zip(outs, out_shapes):
+        o = o.cpu().numpy()
+        if out_pitch_pad:
+            assert (o[:, :, ow:] == 0xA5).all(), "write outside the output rows"
+        res.append(o[:, :, :ow])
+    plan.close()
+    return res
+
+
+def test_config1_vga_frame_bit_exact():
+    """One 640x480 uniform random frame, 3/8 with 11 taps on both axes -> 180x240."""
+    X = synthgen.uniform_frame(2024, 480, 640)
+    hf, of = _filters(3, 8, 11)
+    (Y,) = _run_u8([X[None]], hf, hf)
+    ref = pp.downscale_u8(X, of, of)
+    assert Y.shape == (1, 180, 240)
+    np.testing.assert_array_equal(Y[0], ref)
+
+
+CASES = [
+    # (h, w, p, q, T, kind, starts)
+    (1, 1, 3, 8, 11, "design", None),
+    (3, 5, 3, 8, 11, "random", None),
+    (17, 9, 1, 2, 8, "design", None),
+    (31, 47, 2, 3, 16, "random", None),
+    (45, 130, 4, 9, 7, "random", [-3, 0, 2, 5]),
+    (64, 64, 1, 1, 1, "design", None),
+    (100, 37, 5, 3, 6, "random", None),
+    (129, 257, 3, 8, 16, "random", None),
+    (240, 200, 16, 64, 32, "random", None),
+    (77, 333, 3, 5, 13, "random", [-9, -4, 0]),
+    (540, 960, 3, 8, 11, "design", None),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}-{c[2]}_{c[3]}-T{c[4]}-{c[5]}" for c in CASES])
+def test_odd_shapes_and_ratios_bit_exact(case):
+    h, w, p, q, T, kind, starts = case
+    hf, of = _filters(p, q, T, kind, seed=h * 7 + w, starts=starts)
+    vf, ov = _filters(p, q, T, kind, seed=h * 3 + w + 1, starts=starts)
+    X = synthgen.uniform_frame(h, h, w, idx=w)[None].repeat(2, axis=0)
+    X[1] = 255 - X[1]
+    (Y,) = _run_u8([X], hf, vf)
+    np.testing.assert_array_equal(Y, pp.downscale_u8(X, of, ov))
+
+
+def test_unaligned_pitches_and_guard_bytes():
+    hf, of = _filters(3, 8, 11)
+    vf, ov = _filters(1, 2, 8)
+    X = synthgen.uniform_frame(5, 70, 150, idx=1)[None]
+    (Y,) = _run_u8([X], hf, vf, in_pitch_pad=3, out_pitch_pad=5)
+    np.testing.assert_array_equal(Y, pp.downscale_u8(X, of, ov))
+
+
+def test_i420_frames_every_tile_shape_identical():
+    """Three planes, several frames, every tile shape: identical bytes (independent elementary tasks)."""
+    Yp, Up, Vp = synthgen.yuv420_frames(7, 3, 360, 640)
+    hf, of = _filters(3, 8, 11)
+    ref = [pp.downscale_u8(a, of, of) for a in (Yp, Up, Vp)]
+    for tile in [(16, 16), (32, 16), (16, 32), (32, 32), (64, 16)]:
+        got = _run_u8([Yp, Up, Vp], hf, hf, tile=tile)
+        for g, r in zip(got, ref):
+            np.testing.assert_array_equal(g, r)
+
+
+def test_1080p_i420_bench_launch_sampled_frames():
+    """The benchmark's launch: I420 1080p frames in one launch; every output of several frames checked."""
+    n = 6
+    Yp, Up, Vp = synthgen.yuv420_frames(11, n, 1080, 1920)
+    hf, of = _filters(3, 8, 11)
+    got = _run_u8([Yp, Up, Vp], hf, hf)
+    assert got[0].shape == (n, 405, 720) and got[1].shape == (n, 204, 360)
+    for f in (0, n // 2, n - 1):
+        for g, a in zip(got, (Yp, Up, Vp)):
+            np.testing.assert_array_equal(g[f], pp.downscale_u8(a[f], of, of))
+
+
+def test_constant_frames_map_to_themselves():
+    for (p, q, T) in [(3, 8, 11), (2, 3, 16), (1, 2, 8)]:
+        hf, _ = _filters(p, q, T, "random", seed=T)
+        X = np.broadcast_to(np.arange(256, dtype=np.uint8)[:, None, None], (256, 24, 40)).copy()
+        (Y,) = _run_u8([X], hf, hf)
+        assert (Y == np.arange(256, dtype=np.uint8)[:, None, None]).all()
+
+
+# ------------------------------------------------------------------ float path
+
+def _run_f(planes_u8, hf, vf, fmt, tile=None):
+    shapes = [a.shape[1:] for a in planes_u8]
+    plan = aol.DownscalePlan(shapes, hf, vf, fmt)
+    if tile:
+        plan.set_tile(*tile)
+    ins, outs, bits = [], [], []
+    for a, (oh, ow) in zip(planes_u8, plan.out_shapes):
+        b = synthgen.normalised(a, fmt)
+        bits.append(b)
+        ins.append(torch.from_numpy(b.view(np.int16)).cuda())
+        outs.append(torch.full((a.shape[0], oh, ow), float("nan"), dtype=torch.float32, device="cuda"))
+    plan.run(ins, outs)
+    torch.cuda.synchronize()
+    plan.close()
+    return [o.cpu().numpy() for o in outs], bits
+
+
+def _decode(bits, fmt):
+    if fmt == "bf16":
+        return (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    return bits.view(np.float16).astype(np.float64)
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+def test_float_path_within_tolerance(fmt):
+    Yp, Up, Vp = synthgen.yuv420_frames(3, 2, 270, 480)
+    hf, of = _filters(3, 8, 11)
+    outs, bits = _run_f([Yp, Up, Vp], hf, hf, fmt)
+    for o, b in zip(outs, bits):
+        ref = pp.downscale_f64(_decode(b, fmt), of, of)
+        assert np.isfinite(o).all()
+        err = np.abs(o - ref).max()
+        print(f"{fmt} plane {o.shape}: max-abs error {err:.3e}")
+        assert err <= FLOAT_TOL
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+@pytest.mark.parametrize("case", [(33, 71, 2, 3, 16), (19, 5, 1, 2, 8), (130, 300, 3, 8, 11)])
+def test_float_path_odd_shapes(fmt, case):
+    h, w, p, q, T = case
+    hf, of = _filters(p, q, T)
+    X = synthgen.uniform_frame(h, h, w)[None]
+    (o,), (b,) = _run_f([X], hf, hf, fmt)
+    ref = pp.downscale_f64(_decode(b, fmt), of, of)
+    assert np.abs(o - ref).max() <= FLOAT_TOL
