@@ -167,7 +167,18 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-float", action="store_true")
     ap.add_argument("--only", choices=["u8", "bf16"], default=None, help="run one kernel only (for profiling)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 3 times (scale for HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calib:
+        import torch
+        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes": 1 << 30, "launches": 3}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (frames and streams are "
               "independent repetitions; see the sharding notes). Run with --gpus 1.", file=sys.stderr)

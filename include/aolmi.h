@@ -140,6 +140,11 @@ aol_status aol_plan_destroy(aol_plan* plan);
  * memory. Optional: plans start with about 128 input pixels per tile side. */
 aol_status aol_plan_set_tile(aol_plan* plan, int32_t tile_rx, int32_t tile_ry);
 
+/* Order in which each workgroup walks its contiguous run of tiles inside a
+ * plane: 0 = row-major (horizontal neighbours consecutive, the default),
+ * 1 = column-major. A schedule choice only; results are identical. */
+aol_status aol_plan_set_walk(aol_plan* plan, int32_t order);
+
 /* Integer path (plan precision AOL_PREC_U8). For plane j, d_in[j] points to
  * frame 0 of n_frames frames spaced in_frame_stride[j] elements apart, and
  * d_out[j] to the outputs spaced out_frame_stride[j] apart. Host arrays of
@@ -156,6 +161,103 @@ aol_status aol_downscale_u8(aol_plan* plan, int32_t n_frames, const uint8_t* con
 aol_status aol_downscale_f(aol_plan* plan, int32_t n_frames, const void* const* d_in,
                            const int64_t* in_frame_stride, float* const* d_out,
                            const int64_t* out_frame_stride, hipStream_t stream);
+
+/* --------------------------------------------------------------------------
+ * Batches of video streams (Sec. III: the downscaler repeats for every frame;
+ * Sec. III-A: all elementary tasks are independent, so frames of different
+ * streams may run together). One step downscales one frame of every stream,
+ * each with its own size and filter pair, in one persistent launch.
+ *
+ * Device pointers live in a plan-owned device table written by
+ * aol_batch_set_pointers (a small enqueued kernel: no host synchronisation),
+ * so aol_batch_run -- or a graph captured from it -- is the same launch every
+ * step. Batch buffers must be 16-byte aligned; pitches are in elements. Call
+ * order per step: aol_batch_set_pointers, then aol_batch_run or
+ * aol_graph_launch, on the same stream.
+ * ------------------------------------------------------------------------ */
+typedef struct aol_stream_desc {
+  int64_t height;
+  int64_t width;
+  int64_t in_pitch;  /* elements, or 0 */
+  int64_t out_pitch; /* elements, or 0 */
+  aol_polyphase hf;  /* along lines (copied at plan creation) */
+  aol_polyphase vf;  /* along columns */
+} aol_stream_desc;
+
+typedef struct aol_batch_plan aol_batch_plan;
+typedef struct aol_graph aol_graph;
+
+/* tune_cache: path of a text file of tuned schedules (read here, appended
+ * by aol_autotune), or NULL. All streams use precision prec. */
+aol_status aol_batch_plan_create(int32_t n_streams, const aol_stream_desc* streams, aol_precision prec,
+                                 const char* tune_cache, aol_batch_plan** out);
+aol_status aol_batch_plan_destroy(aol_batch_plan* plan);
+
+/* d_in[i] / d_out[i]: the current frame of stream i (host arrays of device
+ * pointers, length n_streams). Enqueued on stream. */
+aol_status aol_batch_set_pointers(aol_batch_plan* plan, const void* const* d_in, void* const* d_out,
+                                  hipStream_t stream);
+
+/* One step: every stream's frame at the pointers last set. */
+aol_status aol_batch_run(aol_batch_plan* plan, hipStream_t stream);
+
+/* Capture one aol_batch_run into a graph (stream must not be the default
+ * stream). Graphs read the pointer table at run time; re-create them after
+ * aol_autotune, which changes the launch. */
+aol_status aol_batch_graph_create(aol_batch_plan* plan, hipStream_t stream, aol_graph** out);
+aol_status aol_graph_launch(aol_graph* graph, hipStream_t stream);
+aol_status aol_graph_destroy(aol_graph* graph);
+
+/* Times the schedule candidates (segment length x column-band LDS budget)
+ * on the buffers last set, keeps the fastest, and appends it to the tuning
+ * cache. Synchronises the stream (not a run call); results are unchanged. */
+aol_status aol_autotune(aol_batch_plan* plan, hipStream_t stream);
+
+/* The plan's current schedule as a JSON object (plan-owned string). */
+const char* aol_batch_schedule(aol_batch_plan* plan);
+
+/* --------------------------------------------------------------------------
+ * General Array-OL repetition with a weighted-sum elementary task.
+ *
+ * Sec. III-A (tiler footnote): a tiler cuts the pattern of repetition r out of
+ * an array as element i of the pattern = array[(origin + paving.r +
+ * fitting.i) mod array_shape], component-wise with a non-negative modulus.
+ * aol_wsum computes, for every r of the repetition space,
+ *
+ *   out[(o' + P'.r) mod S'] = sum_i w[i] * in[(o + P.r + F.i) mod S]
+ *
+ * in float32 (weights and data float32, accumulation in pattern order with
+ * fused multiply-adds). Arrays are dense row-major float32 buffers owned by
+ * the caller. paving is array_rank x rep_rank, fitting array_rank x pat_rank,
+ * both as [array dim][other dim]; unused entries are ignored. The output
+ * tiler must have a single-element pattern (pat_rank 0) and the same
+ * repetition space, and must write every output element exactly once: this
+ * is checked at plan creation (AOL_ERR_INVALID otherwise). Limits: ranks <= 4,
+ * arrays below 2^31 elements, at most 64 pattern elements.
+ * ------------------------------------------------------------------------ */
+typedef struct aol_tiler {
+  int32_t array_rank;
+  int32_t rep_rank;
+  int32_t pat_rank;
+  int32_t reserved;
+  int64_t array_shape[4];
+  int64_t rep_shape[4];
+  int64_t pat_shape[4];
+  int64_t origin[4];
+  int64_t paving[4][4];
+  int64_t fitting[4][4];
+} aol_tiler;
+
+typedef struct aol_wsum_plan aol_wsum_plan;
+
+/* weights: host, prod(in->pat_shape) float32 in row-major pattern order;
+ * copied into the plan. */
+aol_status aol_wsum_plan_create(const aol_tiler* in, const aol_tiler* out, const float* weights,
+                                aol_wsum_plan** plan);
+/* d_in: the input array (prod(in->array_shape) floats); d_out: the output
+ * array (prod(out->array_shape) floats). Enqueue only. */
+aol_status aol_wsum_run(aol_wsum_plan* plan, const float* d_in, float* d_out, hipStream_t stream);
+aol_status aol_wsum_plan_destroy(aol_wsum_plan* plan);
 
 #ifdef __cplusplus
 }

@@ -7,7 +7,7 @@ PyTorch is used only for device memory and streams: tensors are passed as
 ``data_ptr()`` and ``torch.cuda.current_stream().cuda_stream``; every step
 of the computation runs in the library's HIP kernels.
 
-The library must be built (``python -m paper_1103_4881_amd.build``); when it
+The library must be built (``python paper_1103_4881_amd/build.py``); when it
 is missing, importing this package raises ``ImportError``. There is no CPU
 fallback.
 """
@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libaolmi.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1103_4881_amd.build`")
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_1103_4881_amd/build.py`")
 
 # torch carries its own HIP runtime under the same soname as ROCm's
 # (libamdhip64.so.7). Loading torch first makes the library bind to that one
@@ -84,10 +84,43 @@ _proto("aol_downscale_plan_create", ctypes.c_int, ctypes.POINTER(aol_plane_desc)
        ctypes.POINTER(aol_polyphase), ctypes.POINTER(aol_polyphase), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p))
 _proto("aol_plan_destroy", ctypes.c_int, ctypes.c_void_p)
 _proto("aol_plan_set_tile", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32)
+_proto("aol_plan_set_walk", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32)
 _proto("aol_downscale_u8", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), c_i64p,
        ctypes.POINTER(ctypes.c_void_p), c_i64p, ctypes.c_void_p)
 _proto("aol_downscale_f", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), c_i64p,
        ctypes.POINTER(ctypes.c_void_p), c_i64p, ctypes.c_void_p)
+
+
+class aol_stream_desc(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_int64), ("width", ctypes.c_int64), ("in_pitch", ctypes.c_int64),
+                ("out_pitch", ctypes.c_int64), ("hf", aol_polyphase), ("vf", aol_polyphase)]
+
+
+_proto("aol_batch_plan_create", ctypes.c_int, ctypes.c_int32, ctypes.POINTER(aol_stream_desc), ctypes.c_int,
+       ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p))
+_proto("aol_batch_plan_destroy", ctypes.c_int, ctypes.c_void_p)
+_proto("aol_batch_set_pointers", ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+       ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p)
+_proto("aol_batch_run", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
+_proto("aol_batch_graph_create", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p))
+_proto("aol_graph_launch", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
+_proto("aol_graph_destroy", ctypes.c_int, ctypes.c_void_p)
+_proto("aol_autotune", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
+_proto("aol_batch_schedule", ctypes.c_char_p, ctypes.c_void_p)
+
+
+class aol_tiler(ctypes.Structure):
+    _fields_ = [("array_rank", ctypes.c_int32), ("rep_rank", ctypes.c_int32), ("pat_rank", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
+                ("array_shape", ctypes.c_int64 * 4), ("rep_shape", ctypes.c_int64 * 4),
+                ("pat_shape", ctypes.c_int64 * 4), ("origin", ctypes.c_int64 * 4),
+                ("paving", (ctypes.c_int64 * 4) * 4), ("fitting", (ctypes.c_int64 * 4) * 4)]
+
+
+_proto("aol_wsum_plan_create", ctypes.c_int, ctypes.POINTER(aol_tiler), ctypes.POINTER(aol_tiler),
+       ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_void_p))
+_proto("aol_wsum_run", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_proto("aol_wsum_plan_destroy", ctypes.c_int, ctypes.c_void_p)
 
 
 def _check(status: int):
@@ -169,6 +202,10 @@ def aol_plan_set_tile(plan, tile_rx: int, tile_ry: int):
     _check(_lib.aol_plan_set_tile(plan, tile_rx, tile_ry))
 
 
+def aol_plan_set_walk(plan, order: int):
+    _check(_lib.aol_plan_set_walk(plan, order))
+
+
 def _ptrs(vals):
     return (ctypes.c_void_p * len(vals))(*[int(v) for v in vals])
 
@@ -209,6 +246,9 @@ class DownscalePlan:
     def set_tile(self, tile_rx: int, tile_ry: int):
         aol_plan_set_tile(self._h, tile_rx, tile_ry)
 
+    def set_walk(self, order: int):
+        aol_plan_set_walk(self._h, order)
+
     def close(self):
         if getattr(self, "_h", None):
             aol_plan_destroy(self._h)
@@ -247,3 +287,186 @@ class DownscalePlan:
         fn = aol_downscale_u8 if self.precision == "u8" else aol_downscale_f
         fn(self._h, n, [t.data_ptr() for t in ins], [t.stride(0) for t in ins],
            [o.data_ptr() for o in outs], [o.stride(0) for o in outs], stream)
+
+
+# --------------------------------------------------------------------------
+# generic weighted-sum repetition
+# --------------------------------------------------------------------------
+
+def make_tiler(array_shape, rep_shape, pat_shape, origin, paving, fitting) -> aol_tiler:
+    """Build an ``aol_tiler``; ``paving`` is [array dim][rep dim], ``fitting`` [array dim][pattern dim]."""
+    t = aol_tiler()
+    t.array_rank, t.rep_rank, t.pat_rank = len(array_shape), len(rep_shape), len(pat_shape)
+    for d, v in enumerate(array_shape):
+        t.array_shape[d] = int(v)
+    for k, v in enumerate(rep_shape):
+        t.rep_shape[k] = int(v)
+    for b, v in enumerate(pat_shape):
+        t.pat_shape[b] = int(v)
+    for d, v in enumerate(origin):
+        t.origin[d] = int(v)
+    P = np.asarray(paving, dtype=np.int64).reshape(len(array_shape), len(rep_shape))
+    F = np.asarray(fitting, dtype=np.int64).reshape(len(array_shape), len(pat_shape))
+    for d in range(len(array_shape)):
+        for k in range(len(rep_shape)):
+            t.paving[d][k] = int(P[d, k])
+        for b in range(len(pat_shape)):
+            t.fitting[d][b] = int(F[d, b])
+    return t
+
+
+def identity_out_tiler(rep_shape) -> aol_tiler:
+    d = len(rep_shape)
+    return make_tiler(rep_shape, rep_shape, (), (0,) * d, np.eye(d, dtype=np.int64), np.zeros((d, 0), np.int64))
+
+
+def aol_wsum_plan_create(tin: aol_tiler, tout: aol_tiler, weights):
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+    h = ctypes.c_void_p()
+    _check(_lib.aol_wsum_plan_create(ctypes.byref(tin), ctypes.byref(tout),
+                                     w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(h)))
+    return h
+
+
+def aol_wsum_run(plan, d_in, d_out, stream=None):
+    _check(_lib.aol_wsum_run(plan, ctypes.c_void_p(int(d_in)), ctypes.c_void_p(int(d_out)), _stream_handle(stream)))
+
+
+def aol_wsum_plan_destroy(plan):
+    _check(_lib.aol_wsum_plan_destroy(plan))
+
+
+class WeightedSumPlan:
+    """``out[(o' + P'.r) mod S'] = sum_i w[i] * in[(o + P.r + F.i) mod S]`` on float32 device tensors."""
+
+    def __init__(self, tin: aol_tiler, tout: aol_tiler, weights):
+        self.tin, self.tout = tin, tout
+        self.in_shape = tuple(tin.array_shape[d] for d in range(tin.array_rank))
+        self.out_shape = tuple(tout.array_shape[d] for d in range(tout.array_rank))
+        self._h = aol_wsum_plan_create(tin, tout, weights)
+
+    def run(self, x, y, stream=None):
+        import torch
+        if x.dtype != torch.float32 or y.dtype != torch.float32 or not (x.is_cuda and y.is_cuda):
+            raise ValueError("float32 device tensors expected")
+        if tuple(x.shape) != self.in_shape or tuple(y.shape) != self.out_shape:
+            raise ValueError(f"shapes must be {self.in_shape} -> {self.out_shape}")
+        if not (x.is_contiguous() and y.is_contiguous()):
+            raise ValueError("contiguous tensors expected")
+        aol_wsum_run(self._h, x.data_ptr(), y.data_ptr(), stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            aol_wsum_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------------------
+# batches of streams
+# --------------------------------------------------------------------------
+
+def aol_batch_plan_create(streams, precision="u8", tune_cache=None):
+    """``streams``: list of (height, width, hf, vf[, in_pitch, out_pitch]) with Polyphase filters."""
+    arr = (aol_stream_desc * len(streams))()
+    for i, st in enumerate(streams):
+        h, w, hf, vf = st[:4]
+        ip, op = (st[4], st[5]) if len(st) >= 6 else (0, 0)
+        arr[i] = aol_stream_desc(int(h), int(w), int(ip), int(op), hf.c_struct, vf.c_struct)
+    hnd = ctypes.c_void_p()
+    prec = _PREC[precision] if isinstance(precision, str) else int(precision)
+    _check(_lib.aol_batch_plan_create(len(streams), arr, prec, None if tune_cache is None else tune_cache.encode(),
+                                      ctypes.byref(hnd)))
+    return hnd
+
+
+def aol_batch_plan_destroy(plan):
+    _check(_lib.aol_batch_plan_destroy(plan))
+
+
+def aol_batch_set_pointers(plan, d_in, d_out, stream=None):
+    _check(_lib.aol_batch_set_pointers(plan, _ptrs(d_in), _ptrs(d_out), _stream_handle(stream)))
+
+
+def aol_batch_run(plan, stream=None):
+    _check(_lib.aol_batch_run(plan, _stream_handle(stream)))
+
+
+def aol_batch_graph_create(plan, stream):
+    g = ctypes.c_void_p()
+    _check(_lib.aol_batch_graph_create(plan, _stream_handle(stream), ctypes.byref(g)))
+    return g
+
+
+def aol_graph_launch(graph, stream=None):
+    _check(_lib.aol_graph_launch(graph, _stream_handle(stream)))
+
+
+def aol_graph_destroy(graph):
+    _check(_lib.aol_graph_destroy(graph))
+
+
+def aol_autotune(plan, stream=None):
+    _check(_lib.aol_autotune(plan, _stream_handle(stream)))
+
+
+def aol_batch_schedule(plan) -> str:
+    return _lib.aol_batch_schedule(plan).decode()
+
+
+class BatchPlan:
+    """Many streams, one frame each per step, one persistent launch (optionally a graph)."""
+
+    def __init__(self, streams, precision="u8", tune_cache=None):
+        self.precision = precision
+        self.filters = [(s[2], s[3]) for s in streams]  # keep the coefficient arrays alive
+        self.shapes = [(int(s[0]), int(s[1])) for s in streams]
+        self.out_shapes = [aol_downscale_output_shape(h, w, hf, vf) for (h, w), (hf, vf) in zip(self.shapes, self.filters)]
+        self._h = aol_batch_plan_create(streams, precision, tune_cache)
+        self._graphs = []
+
+    def set_pointers(self, ins, outs, stream=None):
+        import torch
+        for t, (h, w), o, (oh, ow) in zip(ins, self.shapes, outs, self.out_shapes):
+            if not (t.is_cuda and o.is_cuda) or t.shape[-2:] != (h, w) or o.shape[-2:] != (oh, ow):
+                raise ValueError("one [h, w] input and one [out_h, out_w] output device tensor per stream")
+            if not (t.is_contiguous() and o.is_contiguous()):
+                raise ValueError("contiguous tensors expected")
+            if self.precision == "u8" and (t.dtype != torch.uint8 or o.dtype != torch.uint8):
+                raise ValueError("u8 batches take uint8 tensors")
+            if self.precision != "u8" and (t.element_size() != 2 or o.dtype != torch.float32):
+                raise ValueError("float batches take 16-bit inputs and float32 outputs")
+        aol_batch_set_pointers(self._h, [t.data_ptr() for t in ins], [o.data_ptr() for o in outs], stream)
+
+    def run(self, stream=None):
+        aol_batch_run(self._h, stream)
+
+    def graph(self, stream):
+        g = aol_batch_graph_create(self._h, stream)
+        self._graphs.append(g)
+        return g
+
+    def autotune(self, stream=None):
+        aol_autotune(self._h, stream)
+
+    def schedule(self) -> str:
+        return aol_batch_schedule(self._h)
+
+    def close(self):
+        for g in self._graphs:
+            aol_graph_destroy(g)
+        self._graphs = []
+        if getattr(self, "_h", None):
+            aol_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,6 +1,7 @@
 """Build ``libaolmi.so`` (all HIP sources, gfx950) in-tree with hipcc.
 
-Usage: ``python -m paper_1103_4881_amd.build`` or ``build()`` from Python.
+Usage: ``python paper_1103_4881_amd/build.py`` (a path, so the package and its
+library are not imported before the build).
 Every HIP translation unit is compiled with packed fp32 instructions
 disabled; objects go to ``paper_1103_4881_amd/_build/``.
 """

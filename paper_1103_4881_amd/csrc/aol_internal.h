@@ -14,8 +14,11 @@
 namespace aol {
 
 constexpr int kMaxNB = 32;     // output blocks of 16 per tile and axis
+constexpr int kMaxK = 4;       // K-steps (of 4 chunks) per output block
 constexpr int kLanes = 64;     // wavefront width
 constexpr int kChunkBytes = 16;
+constexpr int kWaves = 4;      // waves per workgroup of the fused kernel
+constexpr int kMaxSlots = 12;  // 16-byte tile loads in flight per lane
 
 enum Elem : int32_t { kU8 = 0, kBF16 = 1, kFP16 = 2 };
 
@@ -31,9 +34,12 @@ struct alignas(16) AxisBand {
   int32_t chunk_elems;      // elements per 16-byte chunk (16 for u8, 8 for 16-bit)
   int32_t nchunks;          // chunks touched by any K-step of a full tile
   int32_t split;            // u8: coefficients carried as lo + 128*hi operands
+  int32_t nfrag;            // fragments (64 lanes x 16 B) of the whole band
+  int32_t pad0, pad1, pad2;
   int32_t chunk0[kMaxNB];   // first chunk of block b's window
   int32_t nk[kMaxNB];       // K-steps (4 chunks each) of block b
   int32_t frag[kMaxNB];     // first fragment of block b (64 lanes x 16 B each)
+  int32_t wend[kMaxNB];     // end (exclusive) of block b's nonzero taps, tile-local elements
   int32_t bias[kMaxNB * 16];  // u8: 128*sum(c[phi]) + 128 for each output of the tile
 };
 
@@ -51,6 +57,15 @@ struct PlaneArg {
 
 constexpr int kMaxPlanes = 4;
 
+// Shared-memory layout of one workgroup (byte offsets).
+struct LdsLayout {
+  int32_t frag_h, frag_v;   // coefficient fragments of both axes
+  int32_t bias_h, bias_v;   // int32 biases (u8)
+  int32_t x;                // input tile, xrows x xpitch bytes
+  int32_t z;                // intermediate, transposed: zrows x zpitch elements (hi, then lo)
+  int32_t total;
+};
+
 struct FusedArgs {
   PlaneArg pl[kMaxPlanes];
   int32_t n_planes, n_frames;
@@ -60,9 +75,57 @@ struct FusedArgs {
   const AxisBand* vb;
   const void* hfrag;   // uint8x16 per lane, per fragment
   const void* vfrag;
+  LdsLayout lds;
   int32_t zpitch;      // elements per Z^T row in LDS
   int32_t zrows;       // Z^T rows (tile z-columns, multiple of 16)
   int32_t z_mblocks;   // 16-row blocks of z the horizontal pass computes per full tile
+  int32_t xpitch;      // bytes per input-tile row in LDS
+  int32_t xchunks;     // 16-byte chunks per input-tile row (full tile)
+  int32_t rows_per_load;  // input-tile rows one wave-wide load covers (64 / xchunks)
+  int32_t load_rounds;    // rounds of prefetch slots that stage one full input tile
+  int32_t walk;           // tile order inside a plane: 0 row-major, 1 column-major
+};
+
+// One plane or video stream of the band kernel (device resident). A
+// workgroup owns a column band of `xreps` repetitions (the full width when it
+// fits) and walks a segment of `seg` repetitions down the plane.
+struct BandStream {
+  int32_t h, w, mh, mw;    // input and output sizes
+  int32_t rx, ry;          // repetitions along a line / down the plane
+  int64_t in_pitch, out_pitch;  // elements
+  int32_t ptr;             // index of the input pointer in the pointer table (output follows)
+  int32_t xreps;           // repetitions per column band (multiple of 16)
+  int32_t nbh;             // 16-column blocks of a full band
+  int32_t nch;             // 16-byte chunks staged per input line of a full band
+  uint32_t nch_magic;      // ceil(2^32 / nch)
+  int32_t seg;             // repetitions per segment (multiple of 16)
+  int32_t ring;            // intermediate lines kept (power of two)
+  int32_t rpitch;          // bytes between rows of the ring (of each half for the float form)
+  int32_t zhalf;           // float form: bytes from the hi ring to the lo ring
+  int32_t xpitch;          // bytes between staged lines
+  int32_t lds_x, lds_z, lds_fh, lds_fv, lds_bh, lds_bv;  // LDS byte offsets
+  int32_t vec_in;          // line length a multiple of one chunk and pitch chunk aligned
+  int32_t vec_out;         // output pitch a multiple of 4 elements
+  int32_t pad0, pad1;
+  const AxisBand* hb;      // one period (16 repetitions) of each axis
+  const AxisBand* vb;
+  const void* hfrag;
+  const void* vfrag;
+};
+
+// One unit of work of one frame: stream, column band, segment.
+struct BandUnit {
+  int32_t stream, xb, sy, pad;
+};
+
+struct BandLaunch {
+  const BandStream* streams;
+  const BandUnit* units;         // the units of one frame
+  int32_t units_per_frame, n_frames, total_units;
+  int32_t aligned;               // every pointer 16-byte aligned (inputs) / 16-byte (outputs)
+  void* const* ptr_table;        // device [in, out] pointer per stream, or NULL: use ptrs below
+  const void* ptrs[2 * kMaxPlanes];
+  int64_t fstride[2 * kMaxPlanes];  // elements between frames (in, out) per stream
 };
 
 }  // namespace aol

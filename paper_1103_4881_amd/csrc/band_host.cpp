@@ -1,0 +1,122 @@
+// Host-side construction of the band kernel's descriptors: per-filter period
+// bands, per-plane/stream column band, segment and LDS layout.
+#include "band_host.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace aol {
+
+aol_status build_filter_bands(const FilterHost& hf, const FilterHost& vf, int elem, bool force_split, FilterBands& out) {
+  std::vector<uint8_t> hfr, vfr;
+  AxisBand hb, vb;
+  aol_status st = build_band(hf, 16, elem, true, force_split, hb, hfr, "hf");
+  if (st) return st;
+  st = build_band(vf, 16, elem, false, force_split || hb.split != 0, vb, vfr, "vf");
+  if (st) return st;
+  if (vb.split && !hb.split) {  // one kernel instance carries both axes: same operand layout
+    st = build_band(hf, 16, elem, true, true, hb, hfr, "hf");
+    if (st) return st;
+  }
+  const int E = elem == kU8 ? 16 : 8;
+  // ring: run three periods of the schedule and keep the largest span between
+  // the oldest line a vertical block reads and the newest line written
+  int span = 0, m = 0;
+  for (int B = 0; B < 3 * vb.nblk; ++B) {
+    const int per = B / vb.nblk, lb = B % vb.nblk;
+    const int need = vb.wend[lb] + 16 * per * vb.q;
+    while (16 * m < need) ++m;
+    span = std::max(span, 16 * m - E * vb.chunk0[lb] - 16 * per * vb.q);
+  }
+  int ring = 16;
+  while (ring < span + 16) ring *= 2;
+  out.elem = elem;
+  out.hb = hb;
+  out.vb = vb;
+  out.ring = ring;
+  out.split = hb.split || vb.split;
+  if ((st = out.d_hb.upload(&hb, sizeof hb))) return st;
+  if ((st = out.d_vb.upload(&vb, sizeof vb))) return st;
+  if ((st = out.d_hfrag.upload(hfr.data(), hfr.size()))) return st;
+  if ((st = out.d_vfrag.upload(vfr.data(), vfr.size()))) return st;
+  return AOL_OK;
+}
+
+static int layout(const FilterBands& fb, int nbh, int nch, BandStream& S) {
+  const int es = fb.elem == kU8 ? 1 : 2;
+  S.ring = fb.ring;
+  S.rpitch = fb.ring * es + 16;  // odd multiple of 16 bytes between ring rows
+  if ((S.rpitch / 16) % 2 == 0) S.rpitch += 16;
+  S.xpitch = nch * 16;
+  if ((S.xpitch / 16) % 2 == 0) S.xpitch += 16;
+  S.lds_fh = 0;
+  S.lds_fv = S.lds_fh + fb.hb.nfrag * kLanes * 16;
+  S.lds_bh = S.lds_fv + fb.vb.nfrag * kLanes * 16;
+  S.lds_bv = S.lds_bh + fb.hb.nblk * 16 * 4;
+  S.lds_x = (S.lds_bv + fb.vb.nblk * 16 * 4 + 15) / 16 * 16;
+  S.lds_z = S.lds_x + 16 * S.xpitch;
+  const int zbytes = nbh * 16 * S.rpitch;
+  S.zhalf = fb.elem == kU8 ? 0 : zbytes;
+  return S.lds_z + zbytes * (fb.elem == kU8 ? 1 : 2);
+}
+
+aol_status build_band_stream(const FilterBands& fb, int64_t h, int64_t w, int64_t in_pitch, int64_t out_pitch,
+                             int xreps, int seg, int lds_budget, BandStream& S, int* lds_bytes, int* slots) {
+  memset(&S, 0, sizeof S);
+  const AxisBand& hb = fb.hb;
+  const AxisBand& vb = fb.vb;
+  const int E = fb.elem == kU8 ? 16 : 8;
+  const int64_t rx = (w + hb.q - 1) / hb.q, ry = (h + vb.q - 1) / vb.q;
+  const int full = (int)((rx + 15) / 16 * 16);
+  auto chunks = [&](int xr) {
+    const int nbh = (hb.p * xr + 15) / 16;
+    int nch = 0;
+    for (int b = 0; b < nbh; ++b) {
+      const int per = b / hb.nblk, lb = b % hb.nblk;
+      nch = std::max(nch, hb.chunk0[lb] + per * (hb.q * 16 / E) + 4 * hb.nk[lb]);
+    }
+    return std::make_pair(nbh, nch);
+  };
+  int xr = xreps > 0 ? std::min(xreps, full) : full;
+  int total = 0, nbh = 0, nch = 0;
+  while (true) {
+    std::tie(nbh, nch) = chunks(xr);
+    BandStream T;
+    memset(&T, 0, sizeof T);
+    total = layout(fb, nbh, nch, T);
+    if (total <= lds_budget || xreps > 0 || xr <= 16) {
+      S = T;
+      break;
+    }
+    // halve the band in whole periods
+    const int periods = xr / 16;
+    xr = 16 * std::max(1, (periods + 1) / 2);
+  }
+  if (total > lds_budget) return fail(AOL_ERR_UNSUPPORTED, "a column band of %d repetitions needs %d bytes of LDS", xr, total);
+  const int sl = (16 * nch + 511) / 512;
+  if (sl > 8) return fail(AOL_ERR_UNSUPPORTED, "band lines of %d chunks exceed the staging slots", nch);
+  S.h = (int32_t)h;
+  S.w = (int32_t)w;
+  S.mh = (int32_t)(vb.p * ry);
+  S.mw = (int32_t)(hb.p * rx);
+  S.rx = (int32_t)rx;
+  S.ry = (int32_t)ry;
+  S.in_pitch = in_pitch;
+  S.out_pitch = out_pitch;
+  S.xreps = xr;
+  S.nbh = nbh;
+  S.nch = nch;
+  S.nch_magic = (uint32_t)((((uint64_t)1 << 32) + nch - 1) / nch);
+  S.seg = seg > 0 ? (seg + 15) / 16 * 16 : 16 * std::max(1, (256 + 16 * vb.q - 1) / (16 * vb.q));
+  S.vec_in = (w % E == 0) && (in_pitch % E == 0);
+  S.vec_out = (out_pitch % 4 == 0) && ((hb.p * xr) % 4 == 0);
+  S.hb = (const AxisBand*)fb.d_hb.ptr;
+  S.vb = (const AxisBand*)fb.d_vb.ptr;
+  S.hfrag = fb.d_hfrag.ptr;
+  S.vfrag = fb.d_vfrag.ptr;
+  *lds_bytes = total;
+  *slots = sl;
+  return AOL_OK;
+}
+
+}  // namespace aol

@@ -1,0 +1,412 @@
+// Batched downscaling of many video streams of uneven sizes, ratios and tap
+// counts in one persistent launch per step (one frame of every stream), with
+// a device pointer table so the launch can be captured once in a hipGraph,
+// and an autotuner for the band schedule.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "aolmi.h"
+#include "band_host.h"
+#include "common.h"
+
+using namespace aol;
+
+namespace {
+
+struct Schedule {
+  int seg = 0;         // repetitions per segment (0: about 256 input lines)
+  int budget = 150 * 1024;  // LDS budget per workgroup (picks the column band)
+};
+
+bool same_filter(const FilterHost& a, const FilterHost& b) {
+  return a.p == b.p && a.q == b.q && a.taps == b.taps && a.c == b.c && a.s == b.s;
+}
+
+}  // namespace
+
+struct aol_batch_plan {
+  int n = 0;
+  int elem = kU8;
+  std::vector<aol_stream_desc> desc;  // (filter pointers are not kept)
+  std::vector<FilterHost> hf, vf;
+  std::vector<int> filt;              // filter group of each stream
+  std::vector<FilterBands> bands;     // one per filter group
+  bool split = false;
+  Schedule sched;
+  // built for the current schedule
+  std::vector<BandStream> streams;
+  std::vector<BandUnit> units;
+  int slots = 0, grid = 0;
+  size_t lds = 0;
+  size_t unit_capacity = 0;
+  DeviceBuf d_streams, d_units, d_table;
+  bool pointers_set = false;
+  std::string cache_path, key, sched_json;
+};
+
+struct aol_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
+  std::vector<BandStream> streams(bp->n);
+  int lds = 0, slots = 0;
+  std::vector<std::pair<int64_t, BandUnit>> work;
+  for (int i = 0; i < bp->n; ++i) {
+    const aol_stream_desc& d = bp->desc[i];
+    int l = 0, sl = 0;
+    aol_status st = build_band_stream(bp->bands[bp->filt[i]], d.height, d.width, d.in_pitch, d.out_pitch, 0, sc.seg,
+                                      sc.budget, streams[i], &l, &sl);
+    if (st) return st;
+    streams[i].ptr = i;
+    lds = std::max(lds, l);
+    slots = std::max(slots, sl);
+    const BandStream& S = streams[i];
+    const int nxb = (S.rx + S.xreps - 1) / S.xreps, nsy = (S.ry + S.seg - 1) / S.seg;
+    for (int sy = 0; sy < nsy; ++sy)
+      for (int xb = 0; xb < nxb; ++xb) {
+        const int64_t rows = std::min<int64_t>(S.seg, S.ry - (int64_t)sy * S.seg);
+        const int64_t cols = std::min<int64_t>(S.xreps, S.rx - (int64_t)xb * S.xreps);
+        work.push_back({rows * cols * bp->hf[i].q * bp->vf[i].q, BandUnit{i, xb, sy, 0}});
+      }
+  }
+  // largest units first, so the strided persistent walk ends with small ones;
+  // ties keep streams (and so filters) together
+  std::stable_sort(work.begin(), work.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+  std::vector<BandUnit> units;
+  units.reserve(work.size());
+  for (auto& w : work) units.push_back(w.second);
+  int wg = 0;
+  hipError_t e = band_prepare(bp->elem, slots, bp->split, (size_t)lds, &wg);
+  if (e != hipSuccess) return hip_fail(e, "band kernel attributes");
+  if (wg < 1) return fail(AOL_ERR_UNSUPPORTED, "batch schedule does not fit a compute unit");
+  int dev = 0, cus = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return hip_fail(e, "hipDeviceGetAttribute");
+  // the descriptor buffers keep their addresses across schedules (allocated
+  // once at full capacity), so a graph captured earlier never reads freed memory
+  if (units.size() > bp->unit_capacity) return fail(AOL_ERR_INVALID, "unit capacity exceeded");
+  if ((e = hipMemcpy(bp->d_streams.ptr, streams.data(), sizeof(BandStream) * streams.size(), hipMemcpyHostToDevice)) !=
+      hipSuccess)
+    return hip_fail(e, "hipMemcpy");
+  if ((e = hipMemcpy(bp->d_units.ptr, units.data(), sizeof(BandUnit) * units.size(), hipMemcpyHostToDevice)) !=
+      hipSuccess)
+    return hip_fail(e, "hipMemcpy");
+  bp->streams = std::move(streams);
+  bp->units = std::move(units);
+  bp->lds = (size_t)lds;
+  bp->slots = slots;
+  bp->grid = (int)std::min<int64_t>((int64_t)wg * cus, (int64_t)bp->units.size());
+  bp->sched = sc;
+  char buf[160];
+  snprintf(buf, sizeof buf, "{\"seg\": %d, \"lds_budget\": %d, \"units\": %d, \"grid\": %d, \"lds\": %d}",
+           bp->streams.empty() ? 0 : bp->streams[0].seg, sc.budget, (int)bp->units.size(), bp->grid, lds);
+  bp->sched_json = buf;
+  return AOL_OK;
+}
+
+static aol_status batch_launch(aol_batch_plan* bp, hipStream_t stream) {
+  BandLaunch L;
+  memset(&L, 0, sizeof L);
+  L.streams = (const BandStream*)bp->d_streams.ptr;
+  L.units = (const BandUnit*)bp->d_units.ptr;
+  L.units_per_frame = (int32_t)bp->units.size();
+  L.n_frames = 1;
+  L.total_units = (int32_t)bp->units.size();
+  L.aligned = 1;  // checked by aol_batch_set_pointers
+  L.ptr_table = (void* const*)bp->d_table.ptr;
+  hipError_t e = band_launch(bp->elem, bp->slots, bp->split, L, bp->grid, bp->lds, stream);
+  if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+  return AOL_OK;
+}
+
+// Key of a batch for the tuning cache: device architecture, precision and
+// every stream's geometry and filter.
+static std::string batch_key(const aol_batch_plan* bp) {
+  std::string k;
+  hipDeviceProp_t prop;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) k += prop.gcnArchName;
+  k += "|" + std::to_string(bp->elem);
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the stream descriptions
+  auto mix = [&](int64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (uint64_t)((v >> (8 * i)) & 0xFF);
+      h *= 1099511628211ull;
+    }
+  };
+  for (int i = 0; i < bp->n; ++i) {
+    mix(bp->desc[i].height);
+    mix(bp->desc[i].width);
+    const FilterHost* fs[2] = {&bp->hf[i], &bp->vf[i]};
+    for (const FilterHost* f : fs) {
+      mix(f->p);
+      mix(f->q);
+      mix(f->taps);
+      for (int c : f->c) mix(c);
+      for (int s : f->s) mix(s);
+    }
+  }
+  char buf[32];
+  snprintf(buf, sizeof buf, "|%016llx", (unsigned long long)h);
+  return k + buf;
+}
+
+// Tiny line-oriented cache: "key seg budget" per line.
+static bool cache_lookup(const std::string& path, const std::string& key, Schedule* sc) {
+  FILE* f = fopen(path.c_str(), "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    char k[400];
+    int seg = 0, budget = 0;
+    if (sscanf(line, "%399s %d %d", k, &seg, &budget) == 3 && key == k) {
+      sc->seg = seg;
+      sc->budget = budget;
+      found = true;
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+static void cache_store(const std::string& path, const std::string& key, const Schedule& sc) {
+  FILE* f = fopen(path.c_str(), "a");
+  if (!f) return;
+  fprintf(f, "%s %d %d\n", key.c_str(), sc.seg, sc.budget);
+  fclose(f);
+}
+
+extern "C" {
+
+aol_status aol_batch_plan_create(int32_t n_streams, const aol_stream_desc* streams, aol_precision prec,
+                                 const char* tune_cache, aol_batch_plan** out) {
+  if (!out) return fail(AOL_ERR_INVALID, "NULL plan output");
+  *out = nullptr;
+  if (n_streams < 1 || !streams) return fail(AOL_ERR_INVALID, "need at least one stream");
+  if (n_streams > 4096) return fail(AOL_ERR_UNSUPPORTED, "at most 4096 streams");
+  if (prec != AOL_PREC_U8 && prec != AOL_PREC_BF16 && prec != AOL_PREC_FP16)
+    return fail(AOL_ERR_INVALID, "unknown precision %d", (int)prec);
+  aol_batch_plan* bp = new (std::nothrow) aol_batch_plan();
+  if (!bp) return fail(AOL_ERR_NOMEM, "plan allocation");
+  bp->n = n_streams;
+  bp->elem = prec == AOL_PREC_U8 ? kU8 : prec == AOL_PREC_BF16 ? kBF16 : kFP16;
+  bp->desc.assign(streams, streams + n_streams);
+  bp->hf.resize(n_streams);
+  bp->vf.resize(n_streams);
+  bp->filt.resize(n_streams);
+  aol_status st = AOL_OK;
+  for (int i = 0; i < n_streams && !st; ++i) {
+    aol_stream_desc& d = bp->desc[i];
+    if (d.height < 1 || d.width < 1 || d.height > (1 << 30) || d.width > (1 << 30)) {
+      st = fail(AOL_ERR_INVALID, "stream %d: size %lldx%lld", i, (long long)d.height, (long long)d.width);
+      break;
+    }
+    if ((st = check_filter(&streams[i].hf, "hf", bp->hf[i]))) break;
+    if ((st = check_filter(&streams[i].vf, "vf", bp->vf[i]))) break;
+    const int64_t mw = (int64_t)bp->hf[i].p * ((d.width + bp->hf[i].q - 1) / bp->hf[i].q);
+    if (d.in_pitch == 0) d.in_pitch = d.width;
+    if (d.out_pitch == 0) d.out_pitch = mw;
+    if (d.in_pitch < d.width || d.out_pitch < mw) {
+      st = fail(AOL_ERR_INVALID, "stream %d: pitch smaller than the row", i);
+      break;
+    }
+    d.hf.coeff = nullptr;
+    d.hf.phase_start = nullptr;
+    d.vf.coeff = nullptr;
+    d.vf.phase_start = nullptr;
+  }
+  if (st) {
+    delete bp;
+    return st;
+  }
+  // filter groups; one kernel instance carries every filter, so if one needs
+  // the split integer taps all of them use the split operand layout
+  std::vector<int> rep;
+  for (int i = 0; i < n_streams; ++i) {
+    int gidx = -1;
+    for (size_t g = 0; g < rep.size(); ++g)
+      if (same_filter(bp->hf[rep[g]], bp->hf[i]) && same_filter(bp->vf[rep[g]], bp->vf[i])) gidx = (int)g;
+    if (gidx < 0) {
+      gidx = (int)rep.size();
+      rep.push_back(i);
+    }
+    bp->filt[i] = gidx;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    bp->bands.clear();
+    bp->bands.resize(rep.size());
+    bool any_split = false;
+    for (size_t g = 0; g < rep.size(); ++g) {
+      st = build_filter_bands(bp->hf[rep[g]], bp->vf[rep[g]], bp->elem, pass == 1, bp->bands[g]);
+      if (st) {
+        delete bp;
+        return st;
+      }
+      any_split = any_split || bp->bands[g].split;
+    }
+    bp->split = any_split;
+    if (!any_split || pass == 1) break;
+  }
+  bp->key = batch_key(bp);
+  Schedule sc;
+  if (tune_cache) {
+    bp->cache_path = tune_cache;
+    cache_lookup(bp->cache_path, bp->key, &sc);
+  }
+  // capacity: the most units any schedule can make (bands and segments of 16 repetitions)
+  for (int i = 0; i < n_streams; ++i) {
+    const int64_t rx = (bp->desc[i].width + bp->hf[i].q - 1) / bp->hf[i].q;
+    const int64_t ry = (bp->desc[i].height + bp->vf[i].q - 1) / bp->vf[i].q;
+    bp->unit_capacity += (size_t)(((rx + 15) / 16) * ((ry + 15) / 16));
+  }
+  if (bp->unit_capacity > (size_t)INT_MAX / 2) {
+    delete bp;
+    return fail(AOL_ERR_UNSUPPORTED, "too many units");
+  }
+  st = bp->d_streams.alloc(sizeof(BandStream) * (size_t)n_streams);
+  if (!st) st = bp->d_units.alloc(sizeof(BandUnit) * bp->unit_capacity);
+  if (!st) st = batch_build(bp, sc);
+  if (!st) st = bp->d_table.alloc(sizeof(void*) * 2 * (size_t)n_streams);
+  if (st) {
+    delete bp;
+    return st;
+  }
+  *out = bp;
+  return ok();
+}
+
+aol_status aol_batch_plan_destroy(aol_batch_plan* plan) {
+  delete plan;
+  return ok();
+}
+
+aol_status aol_batch_set_pointers(aol_batch_plan* plan, const void* const* d_in, void* const* d_out,
+                                  hipStream_t stream) {
+  if (!plan) return fail(AOL_ERR_INVALID, "NULL plan");
+  if (!d_in || !d_out) return fail(AOL_ERR_INVALID, "NULL pointer array");
+  std::vector<const void*> ptrs(2 * (size_t)plan->n);
+  for (int i = 0; i < plan->n; ++i) {
+    if (!d_in[i] || !d_out[i]) return fail(AOL_ERR_INVALID, "stream %d: NULL buffer", i);
+    if ((uintptr_t)d_in[i] % 16 || (uintptr_t)d_out[i] % 16)
+      return fail(AOL_ERR_INVALID, "stream %d: batch buffers must be 16-byte aligned", i);
+    ptrs[2 * i] = d_in[i];
+    ptrs[2 * i + 1] = d_out[i];
+  }
+  hipError_t e = set_pointers_launch((void**)plan->d_table.ptr, ptrs.data(), 2 * plan->n, stream);
+  if (e != hipSuccess) return hip_fail(e, "pointer table update");
+  plan->pointers_set = true;
+  return ok();
+}
+
+aol_status aol_batch_run(aol_batch_plan* plan, hipStream_t stream) {
+  if (!plan) return fail(AOL_ERR_INVALID, "NULL plan");
+  if (!plan->pointers_set) return fail(AOL_ERR_INVALID, "aol_batch_set_pointers was never called");
+  aol_status st = batch_launch(plan, stream);
+  return st ? st : ok();
+}
+
+aol_status aol_batch_graph_create(aol_batch_plan* plan, hipStream_t stream, aol_graph** out) {
+  if (!plan || !out) return fail(AOL_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  if (!stream) return fail(AOL_ERR_INVALID, "graph capture needs a non-default stream");
+  aol_graph* g = new (std::nothrow) aol_graph();
+  if (!g) return fail(AOL_ERR_NOMEM, "graph allocation");
+  hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(e, "hipStreamBeginCapture");
+  }
+  aol_status st = batch_launch(plan, stream);
+  e = hipStreamEndCapture(stream, &g->graph);
+  if (st || e != hipSuccess) {
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return st ? st : hip_fail(e, "hipStreamEndCapture");
+  }
+  e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  *out = g;
+  return ok();
+}
+
+aol_status aol_graph_launch(aol_graph* graph, hipStream_t stream) {
+  if (!graph || !graph->exec) return fail(AOL_ERR_INVALID, "NULL graph");
+  hipError_t e = hipGraphLaunch(graph->exec, stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return ok();
+}
+
+aol_status aol_graph_destroy(aol_graph* graph) {
+  if (graph) {
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
+  }
+  return ok();
+}
+
+aol_status aol_autotune(aol_batch_plan* plan, hipStream_t stream) {
+  if (!plan) return fail(AOL_ERR_INVALID, "NULL plan");
+  if (!plan->pointers_set) return fail(AOL_ERR_INVALID, "aol_autotune needs aol_batch_set_pointers first");
+  hipEvent_t e0, e1;
+  hipError_t e;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+  if ((e = hipEventCreate(&e1)) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e, "hipEventCreate");
+  }
+  Schedule best = plan->sched;
+  float best_ms = 1e30f;
+  const int segs[] = {16, 32, 64, 128};
+  const int budgets[] = {150 * 1024, 76 * 1024};
+  aol_status st = AOL_OK;
+  for (int budget : budgets) {
+    for (int seg : segs) {
+      Schedule sc;
+      sc.seg = seg;
+      sc.budget = budget;
+      if (batch_build(plan, sc) != AOL_OK) continue;  // candidate does not fit
+      if ((st = batch_launch(plan, stream))) break;   // warm-up
+      if ((e = hipEventRecord(e0, stream)) != hipSuccess) { st = hip_fail(e, "hipEventRecord"); break; }
+      for (int r = 0; r < 3 && !st; ++r) st = batch_launch(plan, stream);
+      if (st) break;
+      if ((e = hipEventRecord(e1, stream)) != hipSuccess) { st = hip_fail(e, "hipEventRecord"); break; }
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) { st = hip_fail(e, "hipEventSynchronize"); break; }
+      float ms = 0.f;
+      if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { st = hip_fail(e, "hipEventElapsedTime"); break; }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = sc;
+      }
+    }
+    if (st) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  if ((st = batch_build(plan, best))) return st;
+  if (!plan->cache_path.empty()) cache_store(plan->cache_path, plan->key, best);
+  return ok();
+}
+
+const char* aol_batch_schedule(aol_batch_plan* plan) {
+  return plan ? plan->sched_json.c_str() : "";
+}
+
+}  // extern "C"

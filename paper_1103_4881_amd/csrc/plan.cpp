@@ -12,12 +12,14 @@
 
 #include "aol_internal.h"
 #include "aolmi.h"
+#include "band_host.h"
 #include "common.h"
 
 namespace aol {
 
-hipError_t fused_prepare(int elem, size_t lds_bytes);
-hipError_t fused_launch(int elem, const FusedArgs& a, size_t lds_bytes, hipStream_t stream);
+hipError_t fused_prepare(int elem, bool split, int slots, int maxk, size_t lds_bytes, int* wg_per_cu);
+hipError_t fused_launch(int elem, bool split, int slots, int maxk, const FusedArgs& a, int grid, size_t lds_bytes,
+                        hipStream_t stream);
 
 static thread_local std::string g_err;
 
@@ -102,7 +104,7 @@ static uint16_t f32_to_f16_exact(float x, bool* exact) {
   return r;
 }
 
-aol_status build_band(const FilterHost& f, int tr, int elem, bool h_axis, AxisBand& band,
+aol_status build_band(const FilterHost& f, int tr, int elem, bool h_axis, bool force_split, AxisBand& band,
                       std::vector<uint8_t>& frags, const char* name) {
   memset(&band, 0, sizeof band);
   const int E = elem == kU8 ? 16 : 8;
@@ -142,6 +144,7 @@ aol_status build_band(const FilterHost& f, int tr, int elem, bool h_axis, AxisBa
                     elem == kBF16 ? "bf16" : "fp16");
     }
   }
+  split = split || (elem == kU8 && force_split);
   band.split = split ? 1 : 0;
 
   // Per output block: the window of tile-local element positions (position 0
@@ -157,13 +160,18 @@ aol_status build_band(const FilterHost& f, int tr, int elem, bool h_axis, AxisBa
       lo = std::min(lo, st);
       hi = std::max(hi, st + T);
     }
+    band.wend[b] = hi;
     const int c0 = lo / E;
     const int c1 = (hi + E - 1) / E;
     const int nk = (c1 - c0 + 3) / 4;
+    if (nk > kMaxK)
+      return fail(AOL_ERR_UNSUPPORTED, "%s: a block of 16 outputs spans %d input elements (at most %d)", name,
+                  hi - lo, kMaxK * 4 * E - (E - 1));
     band.chunk0[b] = c0;
     band.nk[b] = nk;
     band.frag[b] = nfrag;
     chunk_hi = std::max(chunk_hi, c0 + 4 * nk);
+    const size_t blk_begin = frags.size();
     for (int kb = 0; kb < nk; ++kb) {
       const int parts = split ? 2 : 1;
       const size_t base = frags.size();
@@ -194,6 +202,22 @@ aol_status build_band(const FilterHost& f, int tr, int elem, bool h_axis, AxisBa
       }
       nfrag += 1;
     }
+    // Blocks repeat with the band's period (p outputs per q inputs): reuse an
+    // identical earlier fragment run instead of storing it again.
+    {
+      const size_t len = frags.size() - blk_begin;
+      const size_t fbytes = (size_t)(split ? 2 : 1) * kLanes * 16;
+      for (int pb = 0; pb < b; ++pb) {
+        if (band.nk[pb] != nk) continue;
+        const size_t off = (size_t)band.frag[pb] * fbytes;
+        if (memcmp(&frags[off], &frags[blk_begin], len) == 0) {
+          frags.resize(blk_begin);
+          nfrag -= nk;
+          band.frag[b] = band.frag[pb];
+          break;
+        }
+      }
+    }
     for (int nn = 0; nn < 16; ++nn) {
       const int o = 16 * b + nn;
       int64_t S = 0;
@@ -205,6 +229,7 @@ aol_status build_band(const FilterHost& f, int tr, int elem, bool h_axis, AxisBa
     }
   }
   band.nchunks = chunk_hi;
+  band.nfrag = nfrag * (split ? 2 : 1);
   return AOL_OK;
 }
 
@@ -221,7 +246,20 @@ struct aol_plan {
   int trx = 16, try_ = 16;
   AxisBand hb{}, vb{};
   int zpitch = 0, zrows = 0, zmb = 0;
+  int xpitch = 0, xchunks = 0, rows_per_load = 0;
+  LdsLayout lay{};
   size_t lds = 0;
+  int grid_max = 0;  // workgroups resident on the whole device
+  int slots = 0, maxk = 0, load_rounds = 1;
+  int walk = 0;  // 0: row-major tiles inside a plane, 1: column-major
+  // band schedule: full-width (or column-band) segments streamed down each plane
+  bool use_band = false;
+  int bslots = 0, bgrid = 0, bunits = 0;
+  size_t blds = 0;
+  FilterBands fbands;
+  BandStream bstreams[kMaxPlanes];
+  DeviceBuf d_bstreams, d_bunits;
+  bool split = false;
   DeviceBuf d_hb, d_vb, d_hfrag, d_vfrag;
 };
 
@@ -241,21 +279,25 @@ static int tile_align(const FilterHost& f, int elem, bool h_axis) {
   return h_axis ? E / gcd_int(f.q, E) : 1;
 }
 
-static int default_tile(const FilterHost& f, int elem, bool h_axis) {
+static int default_tile(const FilterHost& f, int elem, bool h_axis, int target = 128) {
   const int al = tile_align(f, elem, h_axis);
-  int tr = (128 + f.q - 1) / f.q;
+  int tr = (target + f.q - 1) / f.q;
   tr = (tr + al - 1) / al * al;
   const int cap = std::max(al, (kMaxNB * 16 / f.p) / al * al);
-  return std::min(tr, cap);
+  return std::max(1, std::min(tr, cap));
 }
 
 static aol_status plan_build_tables(aol_plan* pl, int trx, int try_) {
   AxisBand hb, vb;
   std::vector<uint8_t> hfr, vfr;
-  aol_status st = build_band(pl->hf, trx, pl->elem, true, hb, hfr, "hf");
+  aol_status st = build_band(pl->hf, trx, pl->elem, true, false, hb, hfr, "hf");
   if (st) return st;
-  st = build_band(pl->vf, try_, pl->elem, false, vb, vfr, "vf");
+  st = build_band(pl->vf, try_, pl->elem, false, hb.split != 0, vb, vfr, "vf");
   if (st) return st;
+  if (vb.split && !hb.split) {  // one kernel instance carries both axes: same operand layout
+    st = build_band(pl->hf, trx, pl->elem, true, true, hb, hfr, "hf");
+    if (st) return st;
+  }
   const int E = pl->elem == kU8 ? 16 : 8;
   const int es = pl->elem == kU8 ? 1 : 2;
   // Intermediate lines the vertical pass may read (all K-steps of a full tile).
@@ -263,10 +305,36 @@ static aol_status plan_build_tables(aol_plan* pl, int trx, int try_) {
   int zpitch = zlines;
   if (((zpitch * es) / 16) % 2 == 0) zpitch += 16 / es;  // odd multiple of 16 bytes between LDS rows
   const int zrows = hb.nblk * 16;
-  const size_t lds = (size_t)zrows * zpitch * es * (pl->elem == kU8 ? 1 : 2);
+  // Input tile: the lines of a full tile by the chunks any horizontal K-step reads.
+  const int xchunks = hb.nchunks;
+  if (xchunks > 64) return fail(AOL_ERR_UNSUPPORTED, "tile rows of %d chunks exceed 64", xchunks);
+  int xpitch = xchunks * 16;
+  if ((xpitch / 16) % 2 == 0) xpitch += 16;
+  const int xrows = vb.q * (try_ - 1) + vb.span;
+  const int rpl = 64 / xchunks;
+  const int slots = (xrows + rpl * kWaves - 1) / (rpl * kWaves);  // loads per lane for one input tile
+  int maxk = 1;
+  for (int b = 0; b < hb.nblk; ++b) maxk = std::max(maxk, hb.nk[b]);
+  for (int b = 0; b < vb.nblk; ++b) maxk = std::max(maxk, vb.nk[b]);
+  const bool split = hb.split || vb.split;
+  LdsLayout lay;
+  lay.frag_h = 0;
+  lay.frag_v = lay.frag_h + hb.nfrag * kLanes * 16;
+  lay.bias_h = lay.frag_v + vb.nfrag * kLanes * 16;
+  lay.bias_v = lay.bias_h + hb.nblk * 16 * 4;
+  lay.x = (lay.bias_v + vb.nblk * 16 * 4 + 15) / 16 * 16;
+  lay.z = lay.x + xrows * xpitch;
+  lay.total = lay.z + zrows * zpitch * es * (pl->elem == kU8 ? 1 : 2);
+  const size_t lds = (size_t)lay.total;
   if (lds > 160 * 1024) return fail(AOL_ERR_UNSUPPORTED, "tile %dx%d needs %zu bytes of LDS", trx, try_, lds);
-  hipError_t e = fused_prepare(pl->elem, lds);
-  if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+  int wg_per_cu = 0;
+  hipError_t e = fused_prepare(pl->elem, split, slots, maxk, lds, &wg_per_cu);
+  if (e != hipSuccess) return hip_fail(e, "fused kernel attributes");
+  if (wg_per_cu < 1) return fail(AOL_ERR_UNSUPPORTED, "tile %dx%d does not fit a compute unit", trx, try_);
+  int dev = 0, cus = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return hip_fail(e, "hipDeviceGetAttribute");
   DeviceBuf dhb, dvb, dhf, dvf;
   if ((st = dhb.upload(&hb, sizeof hb))) return st;
   if ((st = dvb.upload(&vb, sizeof vb))) return st;
@@ -279,11 +347,66 @@ static aol_status plan_build_tables(aol_plan* pl, int trx, int try_) {
   pl->zpitch = zpitch;
   pl->zrows = zrows;
   pl->zmb = zlines / 16;
+  pl->xpitch = xpitch;
+  pl->xchunks = xchunks;
+  pl->rows_per_load = rpl;
+  pl->lay = lay;
   pl->lds = lds;
+  pl->grid_max = wg_per_cu * cus;
+  pl->slots = slots;
+  pl->load_rounds = slots <= 6 ? 1 : (slots + kMaxSlots - 1) / kMaxSlots;
+  pl->maxk = maxk;
+  pl->split = split;
   pl->d_hb = std::move(dhb);
   pl->d_vb = std::move(dvb);
   pl->d_hfrag = std::move(dhf);
   pl->d_vfrag = std::move(dvf);
+  return AOL_OK;
+}
+
+// The band schedule (default): one workgroup per column band of a plane,
+// streaming segments down it. Budget: one workgroup of LDS per compute unit.
+static constexpr int kBandLdsBudget = 150 * 1024;
+
+static aol_status plan_build_band(aol_plan* pl, int xreps, int seg) {
+  pl->use_band = false;
+  FilterBands fb;
+  aol_status st = build_filter_bands(pl->hf, pl->vf, pl->elem, false, fb);
+  if (st) return st == AOL_ERR_UNSUPPORTED ? AOL_OK : st;
+  int lds = 0, slots = 0;
+  std::vector<BandUnit> units;
+  for (int i = 0; i < pl->n_planes; ++i) {
+    int l = 0, sl = 0;
+    st = build_band_stream(fb, pl->planes[i].height, pl->planes[i].width, pl->planes[i].in_pitch,
+                           pl->planes[i].out_pitch, xreps, seg, kBandLdsBudget, pl->bstreams[i], &l, &sl);
+    if (st) return st == AOL_ERR_UNSUPPORTED ? AOL_OK : st;
+    pl->bstreams[i].ptr = i;
+    lds = std::max(lds, l);
+    slots = std::max(slots, sl);
+    const BandStream& S = pl->bstreams[i];
+    const int nxb = (S.rx + S.xreps - 1) / S.xreps, nsy = (S.ry + S.seg - 1) / S.seg;
+    for (int sy = 0; sy < nsy; ++sy)
+      for (int xb = 0; xb < nxb; ++xb) units.push_back(BandUnit{i, xb, sy, 0});
+  }
+  int wg = 0;
+  hipError_t e = band_prepare(pl->elem, slots, fb.split, (size_t)lds, &wg);
+  if (e != hipSuccess) return hip_fail(e, "band kernel attributes");
+  if (wg < 1) return AOL_OK;
+  int dev = 0, cus = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return hip_fail(e, "hipDeviceGetAttribute");
+  DeviceBuf ds, du;
+  if ((st = ds.upload(pl->bstreams, sizeof(BandStream) * pl->n_planes))) return st;
+  if ((st = du.upload(units.data(), sizeof(BandUnit) * units.size()))) return st;
+  pl->fbands = std::move(fb);  // moves ownership; the device addresses in the streams stay valid
+  pl->d_bstreams = std::move(ds);
+  pl->d_bunits = std::move(du);
+  pl->bunits = (int)units.size();
+  pl->bslots = slots;
+  pl->blds = (size_t)lds;
+  pl->bgrid = wg * cus;
+  pl->use_band = true;
   return AOL_OK;
 }
 
@@ -353,7 +476,21 @@ aol_status aol_downscale_plan_create(const aol_plane_desc* planes, int32_t n_pla
     pl->mh[i] = mh;
     pl->mw[i] = mw;
   }
-  st = plan_build_tables(pl, default_tile(pl->hf, pl->elem, true), default_tile(pl->vf, pl->elem, false));
+  {
+    // default tile: about 128 input pixels a side, halved (lines first) until
+    // the workgroup's LDS fits 64 KiB
+    int trx = default_tile(pl->hf, pl->elem, true), try_ = default_tile(pl->vf, pl->elem, false);
+    const int al = tile_align(pl->hf, pl->elem, true);
+    while (true) {
+      st = plan_build_tables(pl, trx, try_);
+      if (st == AOL_OK && pl->lds <= 64 * 1024) break;
+      if (st != AOL_OK && st != AOL_ERR_UNSUPPORTED) break;
+      if (try_ > 1) try_ = (try_ + 1) / 2;
+      else if (trx > al) trx = std::max(al, (trx / 2) / al * al);
+      else break;
+    }
+  }
+  if (!st) st = plan_build_band(pl, 0, 0);
   if (st) {
     delete pl;
     return st;
@@ -367,6 +504,13 @@ aol_status aol_plan_destroy(aol_plan* plan) {
   return ok();
 }
 
+aol_status aol_plan_set_walk(aol_plan* plan, int32_t order) {
+  if (!plan) return fail(AOL_ERR_INVALID, "NULL plan");
+  if (order != 0 && order != 1) return fail(AOL_ERR_INVALID, "walk order must be 0 or 1");
+  plan->walk = order;
+  return ok();
+}
+
 aol_status aol_plan_set_tile(aol_plan* plan, int32_t tile_rx, int32_t tile_ry) {
   if (!plan) return fail(AOL_ERR_INVALID, "NULL plan");
   if (tile_rx < 1 || tile_ry < 1) return fail(AOL_ERR_INVALID, "tile repetitions must be >= 1");
@@ -377,6 +521,7 @@ aol_status aol_plan_set_tile(aol_plan* plan, int32_t tile_rx, int32_t tile_ry) {
     return fail(AOL_ERR_UNSUPPORTED, "more than %d outputs per tile", kMaxNB * 16);
   aol_status st = plan_build_tables(plan, tile_rx, tile_ry);
   if (st) return st;
+  plan->use_band = false;  // an explicit tile shape selects the tiled kernel
   return ok();
 }
 
@@ -423,6 +568,31 @@ static aol_status run_fused(aol_plan* plan, int32_t n_frames, const void* const*
   }
   const int64_t total = tiles * n_frames;
   if (total > INT_MAX || tiles > INT_MAX) return fail(AOL_ERR_UNSUPPORTED, "too many tiles in one launch");
+  if (plan->use_band) {
+    BandLaunch L;
+    memset(&L, 0, sizeof L);
+    L.streams = (const BandStream*)plan->d_bstreams.ptr;
+    L.units = (const BandUnit*)plan->d_bunits.ptr;
+    L.units_per_frame = plan->bunits;
+    L.n_frames = n_frames;
+    if ((int64_t)plan->bunits * n_frames > INT_MAX) return fail(AOL_ERR_UNSUPPORTED, "too many units in one launch");
+    L.total_units = plan->bunits * n_frames;
+    bool aligned = true;
+    const int ein = 16 / in_es;
+    for (int i = 0; i < plan->n_planes; ++i) {
+      L.ptrs[2 * i] = d_in[i];
+      L.ptrs[2 * i + 1] = d_out[i];
+      L.fstride[2 * i] = n_frames > 1 ? in_fs[i] : 0;
+      L.fstride[2 * i + 1] = n_frames > 1 ? out_fs[i] : 0;
+      aligned = aligned && (uintptr_t)d_in[i] % 16 == 0 && (uintptr_t)d_out[i] % 16 == 0;
+      if (n_frames > 1) aligned = aligned && in_fs[i] % ein == 0 && out_fs[i] % 4 == 0;
+    }
+    L.aligned = aligned ? 1 : 0;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(L.total_units, plan->bgrid));
+    hipError_t e = band_launch(plan->elem, plan->bslots, plan->fbands.split, L, grid, plan->blds, stream);
+    if (e != hipSuccess) return hip_fail(e, "band kernel launch");
+    return ok();
+  }
   a.n_planes = plan->n_planes;
   a.n_frames = n_frames;
   a.tiles_per_frame = (int32_t)tiles;
@@ -434,7 +604,15 @@ static aol_status run_fused(aol_plan* plan, int32_t n_frames, const void* const*
   a.zpitch = plan->zpitch;
   a.zrows = plan->zrows;
   a.z_mblocks = plan->zmb;
-  hipError_t e = fused_launch(plan->elem, a, plan->lds, stream);
+  a.lds = plan->lay;
+  a.xpitch = plan->xpitch;
+  a.xchunks = plan->xchunks;
+  a.rows_per_load = plan->rows_per_load;
+  a.load_rounds = plan->load_rounds;
+  a.walk = plan->walk;
+  int grid = (int)std::min<int64_t>(total, plan->grid_max);
+  if (grid >= 8) grid -= grid % 8;  // whole rounds over the 8 XCDs
+  hipError_t e = fused_launch(plan->elem, plan->split, plan->slots, plan->maxk, a, grid, plan->lds, stream);
   if (e != hipSuccess) return hip_fail(e, "fused kernel launch");
   return ok();
 }

@@ -84,3 +84,35 @@ def test_single_hip_runtime_in_process():
     with open("/proc/self/maps") as fh:
         paths = {line.split()[-1] for line in fh if "libamdhip64" in line}
     assert len(paths) == 1, paths
+
+
+def test_wsum_validation_on_host():
+    w = np.ones(9, np.float32)
+    good = aol.make_tiler((8, 8), (8, 8), (3, 3), (0, 0), [[1, 0], [0, 1]], [[1, 0], [0, 1]])
+    ident = aol.identity_out_tiler((8, 8))
+    # output tiler that is not a bijection: every repetition writes row 0
+    clash = aol.make_tiler((8, 8), (8, 8), (), (0, 0), [[0, 0], [0, 1]], np.zeros((2, 0), np.int64))
+    _expect(aol.AOL_ERR_INVALID, aol.aol_wsum_plan_create, good, clash, w)
+    # output array of the wrong size
+    small = aol.identity_out_tiler((8, 7))
+    _expect(aol.AOL_ERR_INVALID, aol.aol_wsum_plan_create, good, small, w)
+    # pattern too large
+    big = aol.make_tiler((8, 8), (8, 8), (9, 9), (0, 0), [[1, 0], [0, 1]], [[1, 0], [0, 1]])
+    _expect(aol.AOL_ERR_UNSUPPORTED, aol.aol_wsum_plan_create, big, ident, np.ones(81, np.float32))
+    # rank 5
+    t5 = aol.make_tiler((2, 2, 2, 2), (2, 2, 2, 2), (1,), (0, 0, 0, 0), np.eye(4, dtype=np.int64),
+                        np.zeros((4, 1), np.int64))
+    t5.array_rank = 5
+    _expect(aol.AOL_ERR_UNSUPPORTED, aol.aol_wsum_plan_create, t5, aol.identity_out_tiler((2, 2, 2, 2)), w)
+    # a valid plan needs no device: creation succeeds and destroys cleanly
+    h = aol.aol_wsum_plan_create(good, ident, w)
+    aol.aol_wsum_plan_destroy(h)
+
+
+def test_batch_validation_on_host():
+    good = aol.Polyphase(3, 8, synthgen.design_taps(3, 8, 11))
+    bad = aol.Polyphase(17, 8, np.full((17, 4), 64))
+    _expect(aol.AOL_ERR_INVALID, aol.aol_batch_plan_create, [(0, 64, good, good)], "u8")
+    _expect(aol.AOL_ERR_UNSUPPORTED, aol.aol_batch_plan_create, [(64, 64, good, good), (64, 64, bad, good)], "u8")
+    _expect(aol.AOL_ERR_INVALID, aol.aol_batch_plan_create, [(64, 64, good, good, 10, 0)], "u8")
+    _expect(aol.AOL_ERR_INVALID, aol.aol_batch_run, None, 0)

@@ -110,7 +110,8 @@ def test_i420_frames_every_tile_shape_identical():
     Yp, Up, Vp = synthgen.yuv420_frames(7, 3, 360, 640)
     hf, of = _filters(3, 8, 11)
     ref = [pp.downscale_u8(a, of, of) for a in (Yp, Up, Vp)]
-    for tile in [(16, 16), (32, 16), (16, 32), (32, 32), (64, 16)]:
+    # includes tiles whose output count per side (3*8=24, 3*2=6) is not a multiple of the 16-wide blocks
+    for tile in [(16, 16), (32, 16), (16, 32), (32, 32), (64, 16), (32, 8), (16, 8), (64, 4), (2, 2), (16, 3)]:
         got = _run_u8([Yp, Up, Vp], hf, hf, tile=tile)
         for g, r in zip(got, ref):
             np.testing.assert_array_equal(g, r)
@@ -126,6 +127,20 @@ def test_1080p_i420_bench_launch_sampled_frames():
     for f in (0, n // 2, n - 1):
         for g, a in zip(got, (Yp, Up, Vp)):
             np.testing.assert_array_equal(g[f], pp.downscale_u8(a[f], of, of))
+
+
+@pytest.mark.parametrize("fmt", ["u8", "bf16"])
+@pytest.mark.parametrize("p,q,tile", [(5, 3, (16, 5)), (2, 3, (16, 7)), (3, 8, (4, 3)), (1, 2, (8, 9))])
+def test_tiles_with_partial_output_blocks(fmt, p, q, tile):
+    """Tiles whose p*tile outputs leave a partial 16-wide block: no writes into the neighbouring tile."""
+    X = synthgen.uniform_frame(p * 10 + q, 150, 170)[None]
+    hf, of = _filters(p, q, 9)
+    if fmt == "u8":
+        (Y,) = _run_u8([X], hf, hf, tile=tile)
+        np.testing.assert_array_equal(Y, pp.downscale_u8(X, of, of))
+    else:
+        (o,), (b,) = _run_f([X], hf, hf, fmt, tile=tile)
+        assert np.abs(o - pp.downscale_f64(_decode(b, fmt), of, of)).max() <= FLOAT_TOL
 
 
 def test_constant_frames_map_to_themselves():
