@@ -54,6 +54,35 @@ def alg_bytes_per_frame(in_es, out_es):
     return n_in * in_es + n_out * out_es, oy
 
 
+# ------------------------------------------------------------------ HBM traffic from counters
+
+KERNEL_SOURCES = ["paper_1103_4881_amd/csrc/band.hip", "paper_1103_4881_amd/csrc/aol_internal.h"]
+TRAFFIC_FILE = "profiles/k_band_u8_i420_1080p_300f_traffic.json"
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_bytes():
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a plain 1 GiB copy), or None
+    when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_sha256") != kernel_hash():
+        return None
+    return int(t["fetch_kib"] * 1024 * t["fetch_scale"] + t["write_kib"] * 1024 * t["write_scale"])
+
+
 # ------------------------------------------------------------------ GPU timing
 
 def time_launches(launch, steps, warmup, stream):
@@ -123,6 +152,152 @@ def bench_float(ins_u8, steps, warmup, fmt="bf16", check_frames=(0,)):
                 out_pixels=n * oy[0] * oy[1], max_abs_err=max(errs), err_frames=list(check_frames))
 
 
+# ------------------------------------------------------------------ batch of streams
+
+BATCH_SEED = 2011
+BATCH_STREAMS = 64
+BATCH_FRAMES = 30
+
+
+def bench_batch(fmt="u8", steps=BATCH_FRAMES, warmup=3):
+    """64 streams of uneven sizes/ratios/taps, 30 frames each; one step = one frame of every
+    stream = one pointer-table update + one graph launch of the persistent kernel."""
+    import torch
+    import paper_1103_4881_amd as aol
+    import synthgen
+    mix = synthgen.stream_mix(BATCH_SEED, BATCH_STREAMS)
+    filt = {}
+    streams = []
+    for st in mix:
+        key = (st.p, st.q, st.taps)
+        if key not in filt:
+            filt[key] = aol.Polyphase(st.p, st.q, synthgen.design_taps(st.p, st.q, st.taps))
+        streams.append((st.h, st.w, filt[key], filt[key]))
+    plan = aol.BatchPlan(streams, fmt)
+    # distinct buffers for every frame of every stream (each step reads memory no earlier step read)
+    g = synthgen.rng_for(BATCH_SEED, 1)
+    ins, outs = [], []
+    for i, st in enumerate(mix):
+        base = torch.from_numpy(synthgen.gradient_plane(g, st.h, st.w)).cuda()
+        if fmt != "u8":
+            base = (base.float() / 255.0).to(torch.bfloat16 if fmt == "bf16" else torch.float16)
+        ins.append([base.clone() for _ in range(BATCH_FRAMES)])
+        odt = torch.uint8 if fmt == "u8" else torch.float32
+        outs.append([torch.empty(plan.out_shapes[i], dtype=odt, device="cuda") for _ in range(BATCH_FRAMES)])
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.set_pointers([ins[i][0] for i in range(len(mix))], [outs[i][0] for i in range(len(mix))], s)
+        plan.autotune(s)
+        graph = plan.graph(s)
+
+        def step(k):
+            plan.set_pointers([ins[i][k % BATCH_FRAMES] for i in range(len(mix))],
+                              [outs[i][k % BATCH_FRAMES] for i in range(len(mix))], s)
+            aol.aol_graph_launch(graph, s)
+
+        for k in range(warmup):
+            step(k)
+        s.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t0 = time.perf_counter()
+        for k, (a, b) in enumerate(ev):
+            a.record(s)
+            step(k)
+            b.record(s)
+        s.synchronize()
+        wall = time.perf_counter() - t0
+    per = [a.elapsed_time(b) for a, b in ev]
+    in_es, out_es = (1, 1) if fmt == "u8" else (2, 4)
+    bytes_step = sum(h * w * in_es + oh * ow * out_es for (h, w), (oh, ow) in zip(plan.shapes, plan.out_shapes))
+    px_step = sum(oh * ow for (oh, ow) in plan.out_shapes)
+    ms_step = wall / steps * 1e3
+    ms_kernel = float(np.mean(per))
+    res = {"value": round(px_step / (ms_step / 1e3) / 1e6, 1), "unit": "Mpixel/s", "ms_per_step": round(ms_step, 4),
+           "steps": steps, "streams": len(mix), "frames_per_stream": BATCH_FRAMES,
+           "bytes_per_step": bytes_step, "out_pixels_per_step": px_step,
+           "roofline": {"bound": "hbm", "achieved": round(bytes_step / (ms_kernel / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(bytes_step / (ms_kernel / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+           "schedule": json.loads(plan.schedule())}
+    # correctness of the last step on a few streams against the oracle
+    from oracle import polyphase as pp
+    k = (warmup + steps - 1) % BATCH_FRAMES
+    errs = []
+    for i in range(0, len(mix), 16):
+        st = mix[i]
+        of = pp.Filter(st.p, st.q, synthgen.design_taps(st.p, st.q, st.taps))
+        x = ins[i][k].float().cpu().numpy()
+        y = outs[i][k].float().cpu().numpy()
+        if fmt == "u8":
+            errs.append(float(np.abs(y - pp.downscale_u8(x.astype(np.uint8), of, of)).max()))
+        else:
+            errs.append(float(np.abs(y - pp.downscale_f64(x.astype(np.float64), of, of)).max()))
+    res["max_abs_err_sampled_streams"] = max(errs)
+    plan.close()
+    del ins, outs
+    torch.cuda.empty_cache()
+    return res
+
+
+# ------------------------------------------------------------------ generic repetition
+
+GEN_SHAPE = (64, 1024, 1024)
+
+
+def bench_generic(steps=10, warmup=2):
+    """64x1024x1024 float32, random non-identity tiler, 5x5 weighted sum."""
+    import torch
+    import paper_1103_4881_amd as aol
+    import synthgen
+    from oracle import generic as gn
+    from oracle.arrayol import Tiler
+    rt = synthgen.random_tiler(BATCH_SEED, array_shape=GEN_SHAPE, pat_shape=(5, 5))
+    A = synthgen.rng_for(BATCH_SEED, 1).uniform(-1, 1, size=GEN_SHAPE).astype(np.float32)
+    w = synthgen.rng_for(BATCH_SEED, 2).uniform(-1, 1, size=(5, 5)).astype(np.float32)
+    tin = aol.make_tiler(rt.array_shape, rt.rep_shape, rt.pat_shape, rt.origin, rt.paving, rt.fitting)
+    plan = aol.WeightedSumPlan(tin, aol.identity_out_tiler(rt.rep_shape), w)
+    x = torch.from_numpy(A).cuda()
+    y = torch.empty(plan.out_shape, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    ms_step, ms_kernel, _ = time_launches(lambda: plan.run(x, y), steps, warmup, stream)
+    # footprint: every input element some pattern element reads (bitmap on the device)
+    R = rt.rep_shape
+    seen = torch.zeros(int(np.prod(GEN_SHAPE)), dtype=torch.bool, device="cuda")
+    S = torch.tensor(GEN_SHAPE, device="cuda")
+    strides = torch.tensor([GEN_SHAPE[1] * GEN_SHAPE[2], GEN_SHAPE[2], 1], device="cuda")
+    P = torch.tensor(rt.paving, device="cuda")
+    F = torch.tensor(rt.fitting, device="cuda")
+    o = torch.tensor(rt.origin, device="cuda")
+    for r0 in range(R[0]):
+        r1 = torch.arange(R[1], device="cuda").view(-1, 1)
+        r2 = torch.arange(R[2], device="cuda").view(1, -1)
+        for i0 in range(5):
+            for i1 in range(5):
+                flat = 0
+                for d in range(3):
+                    v = o[d] + P[d, 0] * r0 + P[d, 1] * r1 + P[d, 2] * r2 + F[d, 0] * i0 + F[d, 1] * i1
+                    flat = flat + torch.remainder(v, S[d]) * strides[d]
+                seen[flat.reshape(-1)] = True
+    footprint = int(seen.sum().item())
+    n_out = int(np.prod(R))
+    alg_bytes = 4 * footprint + 4 * n_out
+    # sampled parity against the float64 oracle
+    g = synthgen.rng_for(BATCH_SEED, 3)
+    rs = np.stack([g.integers(0, n, size=4000) for n in R])
+    ref, mag = gn.weighted_sum_at(A, Tiler(rt.array_shape, rt.origin, rt.paving.tolist(), rt.fitting.tolist(),
+                                           rt.pat_shape), w, rs)
+    got = y.cpu().numpy()[tuple(rs)].astype(np.float64)
+    rel = float((np.abs(got - ref) / np.maximum(mag, 1e-30)).max())
+    gbs = alg_bytes / (ms_kernel / 1e3) / 1e9
+    plan.close()
+    return {"value": round(n_out / (ms_step / 1e3) / 1e9, 3), "unit": "Goutput/s", "ms_per_step": round(ms_step, 4),
+            "outputs": n_out, "footprint_elems": footprint, "alg_bytes": alg_bytes,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4)},
+            "max_rel_err_sampled": rel, "tolerance_rel": 1e-5,
+            "tiler": {"paving": rt.paving.tolist(), "fitting": rt.fitting.tolist(), "origin": list(rt.origin),
+                      "rep_shape": list(R)}}
+
+
 # ------------------------------------------------------------------ CPU oracle baseline
 
 _CPU_FRAMES = None
@@ -166,10 +341,17 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=384)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-float", action="store_true")
-    ap.add_argument("--only", choices=["u8", "bf16"], default=None, help="run one kernel only (for profiling)")
+    ap.add_argument("--only", choices=["u8", "bf16", "batch", "generic"], default=None,
+                    help="run one workload only (for profiling)")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-generic", action="store_true")
+    ap.add_argument("--hash", action="store_true", help="print the fused kernel's source hash and exit")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 3 times (scale for HBM byte counters)")
     args = ap.parse_args()
+    if args.hash:
+        print(kernel_hash())
+        return
     if args.copy_calib:
         import torch
         src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
@@ -211,6 +393,20 @@ def main():
         fl = bench_float(ins_u8, args.steps, args.warmup, "bf16")
         log(f"bf16 fused: {fl['ms_step']:.3f} ms/step, kernel {fl['ms_kernel']:.3f} ms, err {fl['max_abs_err']:.2e}")
 
+    extra = {}
+    if not args.no_batch and args.only in (None, "batch"):
+        extra["batch_u8"] = bench_batch("u8")
+        log(f"batch u8: {extra['batch_u8']['ms_per_step']:.3f} ms/step")
+        if not args.no_float:
+            extra["batch_bf16"] = bench_batch("bf16")
+            log(f"batch bf16: {extra['batch_bf16']['ms_per_step']:.3f} ms/step")
+    if not args.no_generic and args.only in (None, "generic"):
+        extra["generic"] = bench_generic()
+        log(f"generic: {extra['generic']['ms_per_step']:.3f} ms/step")
+    if args.only in ("batch", "generic"):
+        print(json.dumps({"metric": METRIC, **extra}), flush=True)
+        return
+
     main_res = u8 if u8 else fl
     dtype = "u8" if u8 else "bf16"
     value = main_res["out_pixels"] / (main_res["ms_step"] / 1e3) / 1e6
@@ -232,7 +428,7 @@ def main():
                    "parallelism": "single GPU"},
         "hbm_frac": round(main_res["bytes"] / (main_res["ms_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic_bytes() if u8 else None,
                      "kernel": "k_fused<u8>" if u8 else "k_fused<bf16>",
                      "alg_bytes_per_launch": main_res["bytes"],
                      "kernel_ms_mean": round(main_res["ms_kernel"], 4)},
@@ -244,6 +440,7 @@ def main():
                        "err_frames": fl["err_frames"],
                        "roofline": {"bound": "hbm", "achieved": round(fgbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                     "frac": round(fgbs / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": fl["bytes"]}}
+    out.update(extra)
     if cpu:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -133,12 +133,22 @@ aol_status aol_downscale_plan_create(const aol_plane_desc* planes, int32_t n_pla
                                      aol_precision prec, aol_plan** out);
 aol_status aol_plan_destroy(aol_plan* plan);
 
-/* Tile shape of a plan in repetitions (tile_rx along lines, tile_ry along
- * columns). tile_rx*hf.q must be a multiple of 16 elements (U8) or 8
+/* Tiled schedule: selects the 2-D tile kernel (input tile with halo and the
+ * intermediate tile in LDS) with this tile shape in repetitions (tile_rx along
+ * lines, tile_ry along columns). tile_rx*hf.q must be a multiple of 16 elements (U8) or 8
  * (float); at most 512 outputs per tile and axis. AOL_ERR_INVALID for a
  * misaligned tile, AOL_ERR_UNSUPPORTED if it would not fit the chip's shared
  * memory. Optional: plans start with about 128 input pixels per tile side. */
 aol_status aol_plan_set_tile(aol_plan* plan, int32_t tile_rx, int32_t tile_ry);
+
+/* Band schedule (the default for every plan that fits it): a workgroup owns a
+ * column band of band_reps repetitions (0: the widest that fits a compute
+ * unit, normally the full width) and streams segments of seg_reps
+ * repetitions (0: about 256 input lines) down the plane, keeping the
+ * intermediate in an LDS ring. Multiples of 16. Selecting a band re-selects
+ * the band kernel after aol_plan_set_tile. AOL_ERR_UNSUPPORTED if the band
+ * does not fit. Results are identical for every schedule. */
+aol_status aol_plan_set_band(aol_plan* plan, int32_t band_reps, int32_t seg_reps);
 
 /* Order in which each workgroup walks its contiguous run of tiles inside a
  * plane: 0 = row-major (horizontal neighbours consecutive, the default),

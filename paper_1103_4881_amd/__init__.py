@@ -85,6 +85,7 @@ _proto("aol_downscale_plan_create", ctypes.c_int, ctypes.POINTER(aol_plane_desc)
 _proto("aol_plan_destroy", ctypes.c_int, ctypes.c_void_p)
 _proto("aol_plan_set_tile", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32)
 _proto("aol_plan_set_walk", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32)
+_proto("aol_plan_set_band", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32)
 _proto("aol_downscale_u8", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), c_i64p,
        ctypes.POINTER(ctypes.c_void_p), c_i64p, ctypes.c_void_p)
 _proto("aol_downscale_f", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), c_i64p,
@@ -202,6 +203,10 @@ def aol_plan_set_tile(plan, tile_rx: int, tile_ry: int):
     _check(_lib.aol_plan_set_tile(plan, tile_rx, tile_ry))
 
 
+def aol_plan_set_band(plan, band_reps: int, seg_reps: int):
+    _check(_lib.aol_plan_set_band(plan, band_reps, seg_reps))
+
+
 def aol_plan_set_walk(plan, order: int):
     _check(_lib.aol_plan_set_walk(plan, order))
 
@@ -245,6 +250,9 @@ class DownscalePlan:
 
     def set_tile(self, tile_rx: int, tile_ry: int):
         aol_plan_set_tile(self._h, tile_rx, tile_ry)
+
+    def set_band(self, band_reps: int = 0, seg_reps: int = 0):
+        aol_plan_set_band(self._h, band_reps, seg_reps)
 
     def set_walk(self, order: int):
         aol_plan_set_walk(self._h, order)

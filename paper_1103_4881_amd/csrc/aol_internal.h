@@ -86,6 +86,8 @@ struct FusedArgs {
   int32_t walk;           // tile order inside a plane: 0 row-major, 1 column-major
 };
 
+constexpr int kBandThreads = 1024;  // threads of a band-kernel workgroup (16 waves)
+
 // One plane or video stream of the band kernel (device resident). A
 // workgroup owns a column band of `xreps` repetitions (the full width when it
 // fits) and walks a segment of `seg` repetitions down the plane.

@@ -42,8 +42,17 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-constexpr int kBandWaves = 8;
-constexpr int kBandThreads = kBandWaves * 64;
+// Workgroup barrier that orders LDS only. __syncthreads() also waits for
+// every outstanding global load (vmcnt(0)), which would drain the register
+// prefetch of the next input lines at each barrier; here global loads stay in
+// flight until their registers are consumed.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+constexpr int kBandWaves = kBandThreads / 64;
 
 __device__ __forceinline__ int bpmod(int x, int m) {
   int r = x % m;
@@ -180,7 +189,9 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
   for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
     const int frame = u / L.units_per_frame;
     const BandUnit U = L.units[u - frame * L.units_per_frame];
-    const BandStream& S = L.streams[U.stream];
+    // by value: kept in scalar registers instead of being re-read from memory
+    // after every global store (the compiler cannot rule out aliasing)
+    const BandStream S = L.streams[U.stream];
     const AxisBand* __restrict__ hb = S.hb;
     const AxisBand* __restrict__ vb = S.vb;
     uint8_t* xs = lds + S.lds_x;
@@ -191,7 +202,7 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
     const int* bv = reinterpret_cast<const int*>(lds + S.lds_bv);
     const int RM = S.ring - 1;
 
-    __syncthreads();  // the previous unit is done with LDS
+    lds_barrier();  // the previous unit is done with LDS
     if (hb != cur_hb) {  // coefficient operands and biases of this stream's filter
       cur_hb = hb;
       const v4i* gh = reinterpret_cast<const v4i*>(S.hfrag);
@@ -229,10 +240,38 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
       G.vec_out = S.vec_out && L.aligned;
     }
 
+    // loads run AHEAD steps ahead: two stagers alternate (narrow lines), or
+    // one stager is issued at the start of a step and committed in its middle
+    constexpr int AHEAD = SLOTS <= 2 ? 2 : 1;
     int B = 0;  // next vertical block
     auto step = [&](int m, BandStager<ELEM, SLOTS>& mine, BandStager<ELEM, SLOTS>& other) {
-      if (m + 2 < G.M) mine.issue(S, G, m + 2, tid);  // in flight for two steps
+      if (m + AHEAD < G.M) mine.issue(S, G, m + AHEAD, tid);
       // ---- horizontal pass: 16 intermediate lines of every 16-column block
+      if constexpr (ELEM == kU8 && !split && SLOTS <= 2) {
+        // two blocks per iteration: their LDS reads and MFMAs overlap
+        for (int b0 = wave; b0 < G.nbh; b0 += 2 * kBandWaves) {
+          const int b1 = b0 + kBandWaves;
+          const bool two = b1 < G.nbh;
+          const int per0 = b0 / hb->nblk, lb0 = b0 - per0 * hb->nblk;
+          const int per1 = two ? b1 / hb->nblk : per0, lb1 = two ? b1 - per1 * hb->nblk : lb0;
+          const int c00 = hb->chunk0[lb0] + per0 * hb->q, c01 = hb->chunk0[lb1] + per1 * hb->q;
+          const int nk0 = hb->nk[lb0], nk1 = two ? hb->nk[lb1] : 0;
+          const int fb0 = hb->frag[lb0], fb1 = hb->frag[lb1];
+          const uint8_t* xr = xs + n * S.xpitch;
+          v4i acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+          const int nkm = nk0 > nk1 ? nk0 : nk1;
+          for (int kb = 0; kb < nkm; ++kb) {
+            v4i a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+            if (kb < nk0) a0 = *reinterpret_cast<const v4i*>(xr + (c00 + 4 * kb + g) * 16);
+            if (kb < nk1) a1 = *reinterpret_cast<const v4i*>(xr + (c01 + 4 * kb + g) * 16);
+            if (kb < nk0) acc0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(b_to_i8(a0), fh[(fb0 + kb) * 64 + lane], acc0, 0, 0, 0);
+            if (kb < nk1) acc1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(b_to_i8(a1), fh[(fb1 + kb) * 64 + lane], acc1, 0, 0, 0);
+          }
+          const int zoff = (16 * m + 4 * g) & RM;
+          *reinterpret_cast<uint32_t*>(zs + (16 * b0 + n) * S.rpitch + zoff) = b_quant4(acc0, bh[lb0 * 16 + n]);
+          if (two) *reinterpret_cast<uint32_t*>(zs + (16 * b1 + n) * S.rpitch + zoff) = b_quant4(acc1, bh[lb1 * 16 + n]);
+        }
+      } else
       for (int b = wave; b < G.nbh; b += kBandWaves) {
         const int per = b / hb->nblk, lb = b - per * hb->nblk;
         const int c0 = hb->chunk0[lb] + per * (hb->q * 16 / E);  // a period is 16q elements
@@ -266,7 +305,7 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
           *reinterpret_cast<uint2*>(zp + S.zhalf) = uint2{l01, l23};
         }
       }
-      __syncthreads();  // staging consumed, intermediate lines written
+      lds_barrier();  // staging consumed, intermediate lines written
       if (m + 1 < G.M) other.commit(S, xs, tid);
       // ---- vertical blocks whose window is complete
       const int have = min(G.Lz, 16 * (m + 1));
@@ -325,7 +364,7 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
         }
         ++B;
       }
-      __syncthreads();  // ring reads of this step done, next staging committed
+      lds_barrier();  // ring reads of this step done, next staging committed
     };
 
     if constexpr (ELEM != kU8) {
@@ -336,12 +375,16 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
       }
     }
     s0.issue(S, G, 0, tid);
-    if (G.M > 1) s1.issue(S, G, 1, tid);
+    if (AHEAD == 2 && G.M > 1) s1.issue(S, G, 1, tid);
     s0.commit(S, xs, tid);
-    __syncthreads();
-    for (int m = 0; m < G.M; m += 2) {
-      step(m, s0, s1);
-      if (m + 1 < G.M) step(m + 1, s1, s0);
+    lds_barrier();
+    if constexpr (AHEAD == 2) {
+      for (int m = 0; m < G.M; m += 2) {
+        step(m, s0, s1);
+        if (m + 1 < G.M) step(m + 1, s1, s0);
+      }
+    } else {
+      for (int m = 0; m < G.M; ++m) step(m, s0, s0);
     }
   }
 }
@@ -350,8 +393,8 @@ using BandFn = void (*)(BandLaunch);
 
 template <int ELEM>
 static BandFn band_pick_e(int slots, bool split) {
-  if (slots <= 4) return split ? k_band<ELEM, 4, true> : k_band<ELEM, 4, false>;
-  return split ? k_band<ELEM, 8, true> : k_band<ELEM, 8, false>;
+  if (slots <= 2) return split ? k_band<ELEM, 2, true> : k_band<ELEM, 2, false>;
+  return split ? k_band<ELEM, 4, true> : k_band<ELEM, 4, false>;
 }
 
 static BandFn band_pick(int elem, int slots, bool split) {

@@ -93,8 +93,8 @@ aol_status build_band_stream(const FilterBands& fb, int64_t h, int64_t w, int64_
     xr = 16 * std::max(1, (periods + 1) / 2);
   }
   if (total > lds_budget) return fail(AOL_ERR_UNSUPPORTED, "a column band of %d repetitions needs %d bytes of LDS", xr, total);
-  const int sl = (16 * nch + 511) / 512;
-  if (sl > 8) return fail(AOL_ERR_UNSUPPORTED, "band lines of %d chunks exceed the staging slots", nch);
+  const int sl = (16 * nch + kBandThreads - 1) / kBandThreads;
+  if (sl > 4) return fail(AOL_ERR_UNSUPPORTED, "band lines of %d chunks exceed the staging slots", nch);
   S.h = (int32_t)h;
   S.w = (int32_t)w;
   S.mh = (int32_t)(vb.p * ry);

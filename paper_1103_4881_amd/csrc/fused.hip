@@ -41,6 +41,16 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
+// Workgroup barrier that orders LDS only. __syncthreads() also waits for
+// every outstanding global load (vmcnt(0)), which would drain the register
+// prefetch of the next input lines at each barrier; here global loads stay in
+// flight until their registers are consumed.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ int pmod(int x, int m) {
   int r = x % m;
   return r < 0 ? r + m : r;
@@ -461,7 +471,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_fused(FusedArgs a) {
     st.issue(a, g, wave, lr, lc, r);
     st.commit(a, g, wave, lr, lc, lds + a.lds.x, r);
   }
-  __syncthreads();
+  lds_barrier();
 
   while (true) {
     const int tn = walk.pop();
@@ -471,7 +481,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_fused(FusedArgs a) {
       st.issue(a, gn, wave, lr, lc, 0);  // in flight during this tile's passes
     }
     h_pass<ELEM, SPLIT, MAXK>(a, g, hb, lds, wave, lane);
-    __syncthreads();  // input tile consumed, intermediate complete
+    lds_barrier();  // input tile consumed, intermediate complete
     if (tn >= 0) {
       st.commit(a, gn, wave, lr, lc, lds + a.lds.x, 0);
       for (int r = 1; r < a.load_rounds; ++r) {  // tiles larger than one round of loads
@@ -480,7 +490,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_fused(FusedArgs a) {
       }
     }
     v_pass<ELEM, SPLIT, MAXK>(a, g, hb, vb, lds, wave, lane);
-    __syncthreads();  // intermediate consumed, next input tile staged
+    lds_barrier();  // intermediate consumed, next input tile staged
     if (tn < 0) break;
     g = gn;
   }

@@ -504,6 +504,16 @@ aol_status aol_plan_destroy(aol_plan* plan) {
   return ok();
 }
 
+aol_status aol_plan_set_band(aol_plan* plan, int32_t band_reps, int32_t seg_reps) {
+  if (!plan) return fail(AOL_ERR_INVALID, "NULL plan");
+  if (band_reps < 0 || seg_reps < 0 || band_reps % 16 || seg_reps % 16)
+    return fail(AOL_ERR_INVALID, "band and segment repetitions must be multiples of 16 (or 0)");
+  aol_status st = plan_build_band(plan, band_reps, seg_reps);
+  if (st) return st;
+  if (!plan->use_band) return fail(AOL_ERR_UNSUPPORTED, "this band shape does not fit a compute unit");
+  return ok();
+}
+
 aol_status aol_plan_set_walk(aol_plan* plan, int32_t order) {
   if (!plan) return fail(AOL_ERR_INVALID, "NULL plan");
   if (order != 0 && order != 1) return fail(AOL_ERR_INVALID, "walk order must be 0 or 1");

@@ -198,3 +198,39 @@ def test_float_path_odd_shapes(fmt, case):
     (o,), (b,) = _run_f([X], hf, hf, fmt)
     ref = pp.downscale_f64(_decode(b, fmt), of, of)
     assert np.abs(o - ref).max() <= FLOAT_TOL
+
+
+@pytest.mark.parametrize("band,seg", [(0, 0), (16, 16), (64, 16), (128, 64), (32, 32)])
+def test_band_schedules_bit_exact(band, seg):
+    """Band kernel: column bands with halo chunks, several segment lengths, I420 frames."""
+    Yp, Up, Vp = synthgen.yuv420_frames(13, 2, 270, 700)
+    hf, of = _filters(3, 8, 11)
+    vf, ov = _filters(2, 3, 14)
+    shapes = [a.shape[1:] for a in (Yp, Up, Vp)]
+    plan = aol.DownscalePlan(shapes, hf, vf, "u8")
+    plan.set_band(band, seg)
+    ins = [torch.from_numpy(a).cuda() for a in (Yp, Up, Vp)]
+    outs = [torch.full((2,) + s, 0xA5, dtype=torch.uint8, device="cuda") for s in plan.out_shapes]
+    plan.run(ins, outs)
+    torch.cuda.synchronize()
+    for o, a in zip(outs, (Yp, Up, Vp)):
+        np.testing.assert_array_equal(o.cpu().numpy(), pp.downscale_u8(a, of, ov))
+    plan.close()
+
+
+@pytest.mark.parametrize("fmt,band,seg", [("bf16", 0, 0), ("bf16", 32, 16), ("fp16", 16, 48)])
+def test_band_schedules_float(fmt, band, seg):
+    Yp, _, _ = synthgen.yuv420_frames(17, 2, 200, 520)
+    hf, of = _filters(3, 8, 11)
+    plan = aol.DownscalePlan([Yp.shape[1:]], hf, hf, fmt)
+    plan.set_band(band, seg)
+    b = synthgen.normalised(Yp, fmt)
+    ins = [torch.from_numpy(b.view(np.int16)).cuda()]
+    outs = [torch.full((2,) + plan.out_shapes[0], float("nan"), dtype=torch.float32, device="cuda")]
+    plan.run(ins, outs)
+    torch.cuda.synchronize()
+    ref = pp.downscale_f64(_decode(b, fmt), of, of)
+    got = outs[0].cpu().numpy()
+    assert np.isfinite(got).all()
+    assert np.abs(got - ref).max() <= FLOAT_TOL
+    plan.close()
