@@ -86,7 +86,9 @@ struct FusedArgs {
   int32_t walk;           // tile order inside a plane: 0 row-major, 1 column-major
 };
 
-constexpr int kBandThreads = 1024;  // threads of a band-kernel workgroup (16 waves)
+constexpr int kBandThreads = 1024;     // threads of a band-kernel workgroup (16 waves)
+constexpr int kBandLoadThreads = 512;  // waves 0-7 stream input lines into LDS, waves 8-15 compute
+constexpr int kBandMaxSlots = 8;       // 16-byte chunks per loading lane and staged step
 
 // One plane or video stream of the band kernel (device resident). A
 // workgroup owns a column band of `xreps` repetitions (the full width when it

@@ -15,7 +15,14 @@
 //    transposed, into a ring in LDS spanning the band;
 //  * whenever the ring holds the window of the next 16 output lines, the
 //    vertical pass runs on it and stores them; the vertical halo never leaves
-//    the chip. Loads run two steps ahead in registers.
+//    the chip.
+//
+// The workgroup's waves have two roles. Waves 0-7 only load: they keep the
+// next few steps of input lines in flight in registers and write step m+1
+// into the staging lines while waves 8-15 run the vertical pass of step m.
+// Waves 8-15 only compute and store. A gfx9 wave with both loads and stores
+// outstanding can only wait for all of them, so mixing the roles would drain
+// the prefetch at every step.
 //
 // Operands: A = 16 lines x (4 chunks of 16 bytes per K-step), one chunk per
 // lane; B = the coefficients of one 16-output block in lane order, prepared
@@ -52,7 +59,31 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-constexpr int kBandWaves = kBandThreads / 64;
+
+// Pointers read from memory (descriptor and pointer tables) are generic to
+// the compiler, and generic accesses become flat instructions, which count
+// against both the vector-memory and the LDS counters: every wait for LDS
+// would also wait for the prefetched input lines. Device data is therefore
+// accessed through global (1) and constant (4) address-space pointers; the
+// constant ones also let uniform descriptor reads go through the scalar unit.
+#define AOL_GLOBAL __attribute__((address_space(1)))
+#define AOL_CONST __attribute__((address_space(4)))
+typedef const AOL_GLOBAL uint8_t* gsrc_t;
+typedef AOL_GLOBAL uint8_t* gdst_t;
+typedef const AOL_CONST AxisBand* cband_t;
+
+// A copy of a device-resident descriptor read through the constant address
+// space (scalar loads when the address is uniform).
+template <class T>
+__device__ __forceinline__ T load_const(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "descriptor of whole words");
+  T v;
+  const AOL_CONST uint32_t* src = (const AOL_CONST uint32_t*)p;
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = src[i];
+  return v;
+}
 
 __device__ __forceinline__ int bpmod(int x, int m) {
   int r = x % m;
@@ -60,7 +91,7 @@ __device__ __forceinline__ int bpmod(int x, int m) {
 }
 
 template <int ES>
-__device__ __attribute__((noinline)) v4i b_load_chunk_wrap(const uint8_t* row, int col, int w) {
+__device__ __attribute__((noinline)) v4i b_load_chunk_wrap(gsrc_t row, int col, int w) {
   v4i r;
   if constexpr (ES == 1) {
 #pragma unroll
@@ -71,7 +102,7 @@ __device__ __attribute__((noinline)) v4i b_load_chunk_wrap(const uint8_t* row, i
       r[d] = (int)v;
     }
   } else {
-    const uint16_t* r16 = reinterpret_cast<const uint16_t*>(row);
+    const AOL_GLOBAL uint16_t* r16 = (const AOL_GLOBAL uint16_t*)row;
 #pragma unroll
     for (int d = 0; d < 4; ++d)
       r[d] = (int)((uint32_t)r16[bpmod(col + 2 * d, w)] | ((uint32_t)r16[bpmod(col + 2 * d + 1, w)] << 16));
@@ -126,74 +157,216 @@ __device__ __forceinline__ float b_hi16(uint32_t v) {
 
 // Per-unit geometry (uniform across the workgroup).
 struct BandUnitGeo {
-  const uint8_t* src;
-  uint8_t* dst;
+  gsrc_t src;
+  gdst_t dst;
   int zrow0, Lz, M, NBV, a0, orow0, ocol0, row_end, col_end, nbh;
   int vec_in, vec_out;
 };
 
+// Prefetch depth (staged steps in flight) for a number of chunks per loading
+// lane and step: about 64 registers of input in flight per loading lane.
+template <int SLOTS>
+struct BandDepth {
+  static constexpr int value = SLOTS <= 1 ? 8 : SLOTS <= 2 ? 6 : SLOTS <= 4 ? 3 : 1;
+};
+
+// The loading waves: each lane owns SLOTS chunks of every staged step (16
+// input lines of the band, line-major), fixed for the unit. Every load is
+// unconditional: a lane without a chunk, or a line past the unit's window,
+// loads a line that another lane of the same step also loads (a cache hit,
+// no extra HBM traffic), so the in-flight counts stay exact.
 template <int ELEM, int SLOTS>
-struct BandStager {
+struct BandFeed {
   static constexpr int ES = ELEM == kU8 ? 1 : 2;
   static constexpr int E = 16 / ES;
-  v4i pre[SLOTS];
-  // the 16 lines of step m, chunks of the band, into registers; slot s of
-  // thread t is chunk t + s*threads of the step, line-major
-  __device__ __forceinline__ void issue(const BandStream& S, const BandUnitGeo& u, int m, int tid) {
+  int r[SLOTS];    // line of the step
+  int col[SLOTS];  // first element of the chunk, wrapped into the line
+  int xo[SLOTS];   // LDS byte offset of the chunk in the staging lines
+
+  __device__ __forceinline__ void setup(const BandStream& S, const BandUnitGeo& G, int ltid) {
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-      const int idx = tid + s * kBandThreads;
-      const int r = (int)__umulhi((uint32_t)idx, S.nch_magic);  // idx / nch
-      const int c = idx - r * S.nch;
-      v4i v = {0, 0, 0, 0};
-      if (r < 16 && 16 * m + r < u.Lz) {
-        int grow = u.zrow0 + 16 * m + r;
-        if (grow < 0 || grow >= S.h) grow = bpmod(grow, S.h);
-        const uint8_t* rp = u.src + (int64_t)grow * S.in_pitch * ES;
-        int col = u.a0 + c * E;
-        if (u.vec_in) {
-          // whole chunks of a circular line: a wrapped chunk is another chunk
-          while (col < 0) col += S.w;
-          while (col >= S.w) col -= S.w;
-          v = *reinterpret_cast<const v4i*>(rp + (int64_t)col * ES);
-        } else {
-          v = b_load_chunk_wrap<ES>(rp, col, S.w);
-        }
-      }
-      pre[s] = v;
+      const int idx = ltid + s * kBandLoadThreads;
+      int rr = (int)__umulhi((uint32_t)idx, S.nch_magic);  // idx / nch
+      int c = idx - rr * S.nch;
+      // a lane past the last chunk loads and stores chunk 0 of line 15 again:
+      // the same bytes to the same place, and no branch around the store,
+      // which would leave its register's load outstanding on the other path
+      if (rr >= 16) { rr = 15; c = 0; }
+      xo[s] = rr * S.xpitch + c * 16;
+      r[s] = rr;
+      int cl = G.a0 + c * E;
+      if (cl < 0 || cl >= S.w) cl = bpmod(cl, S.w);
+      col[s] = cl;
     }
   }
-  __device__ __forceinline__ void commit(const BandStream& S, uint8_t* xs, int tid) {
+
+  __device__ __forceinline__ gsrc_t line(const BandStream& S, const BandUnitGeo& G, int m, int s) const {
+    const int l = min(16 * m + r[s], G.Lz - 1);
+    int grow = G.zrow0 + l;
+    if (grow < 0 || grow >= S.h) grow = bpmod(grow, S.h);
+    return G.src + (int64_t)grow * S.in_pitch * ES;
+  }
+
+  // Whole chunks of a circular line (a wrapped chunk is another chunk).
+  // Straight-line code with the same loads on every path, so the compiler's
+  // count of loads in flight stays exact: rows are clamped and wrapped with
+  // arithmetic, and a step past the unit loads its last line again.
+  __device__ __forceinline__ void issue(v4i (&pre)[SLOTS], const BandStream& S, const BandUnitGeo& G, int m) const {
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-      const int idx = tid + s * kBandThreads;
-      const int r = (int)__umulhi((uint32_t)idx, S.nch_magic);
-      const int c = idx - r * S.nch;
-      if (r < 16) *reinterpret_cast<v4i*>(xs + r * S.xpitch + c * 16) = pre[s];
+      const int grow = bpmod(G.zrow0 + min(16 * m + r[s], G.Lz - 1), S.h);
+      pre[s] = *(const AOL_GLOBAL v4i*)(G.src + ((int64_t)grow * S.in_pitch + col[s]) * ES);
     }
+  }
+
+  // lines whose chunks are not whole chunks of the line: gathered element by
+  // element with the wrap (a call, which waits for every load it issues)
+  // and staged at once
+  __device__ __forceinline__ void stage_gathered(const BandStream& S, const BandUnitGeo& G, int m, uint8_t* xs) const {
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const v4i a = b_load_chunk_wrap<ES>(line(S, G, m, s), col[s], S.w);
+      *reinterpret_cast<v4i*>(xs + xo[s]) = a;
+    }
+  }
+
+  __device__ __forceinline__ void commit(const v4i (&pre)[SLOTS], uint8_t* xs) const {
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) *reinterpret_cast<v4i*>(xs + xo[s]) = pre[s];
   }
 };
+
+// Loading waves of one unit: keep D steps of input lines in flight in
+// registers and commit step m+1 into the staging lines while the compute
+// waves run the vertical pass of step m. These waves issue no stores to
+// memory, so their waits on loads count exactly (on gfx9 a wave with loads
+// and stores outstanding can only wait for all of them).
+template <int ELEM, int SLOTS>
+__device__ __forceinline__ void band_feed_unit(const BandFeed<ELEM, SLOTS>& F, const BandStream& S,
+                                               const BandUnitGeo& G, uint8_t* xs) {
+  constexpr int D = BandDepth<SLOTS>::value;
+  v4i pre[D][SLOTS];
+#pragma unroll
+  for (int k = 0; k < D; ++k) F.issue(pre[k], S, G, k);
+  F.commit(pre[0], xs);
+  F.issue(pre[0], S, G, D);
+  lds_barrier();  // step 0 staged
+  // Every iteration commits and re-issues one register set, so the loads in
+  // flight at the loop head are the same sets in the same order on entry and
+  // on the back edge. Steps past the unit stage its last line again into
+  // staging lines nobody reads any more.
+  // The loop runs whole groups of D steps, without an exit in between (an
+  // exit path would reach the loop head with other loads in flight).
+  int m0 = 0;
+  for (; m0 + D <= G.M; m0 += D) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      lds_barrier();  // horizontal pass of step m0+k done with the staging lines
+      const int j = (k + 1) % D;  // a constant once the loop is unrolled
+      F.commit(pre[j], xs);
+      F.issue(pre[j], S, G, m0 + k + 1 + D);
+      lds_barrier();  // step m0+k+1 staged
+    }
+  }
+#pragma unroll
+  for (int k = 0; k + 1 < D; ++k) {
+    if (m0 + k < G.M) {
+      lds_barrier();
+      F.commit(pre[(k + 1) % D], xs);
+      lds_barrier();
+    }
+  }
+  // nothing of this unit stays in flight into the next one
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+}
+
+// The same for lines that are gathered element by element: no prefetch.
+template <int ELEM, int SLOTS>
+__device__ __forceinline__ void band_feed_unit_gathered(const BandFeed<ELEM, SLOTS>& F, const BandStream& S,
+                                                                  const BandUnitGeo& G, uint8_t* xs) {
+  F.stage_gathered(S, G, 0, xs);
+  lds_barrier();  // step 0 staged
+  for (int m = 0; m < G.M; ++m) {
+    lds_barrier();  // horizontal pass of step m done with the staging lines
+    if (m + 1 < G.M) F.stage_gathered(S, G, m + 1, xs);
+    lds_barrier();  // step m+1 staged
+  }
+}
+
+// Stream descriptor and geometry of unit u (of the whole launch: units of
+// one frame, repeated over frames).
+template <int ELEM>
+__device__ __forceinline__ void band_unit(const BandLaunch& L, int u, BandStream& S, BandUnitGeo& G) {
+  constexpr int ES = ELEM == kU8 ? 1 : 2;
+  const int frame = u / L.units_per_frame;
+  const BandUnit U = load_const(L.units + (u - frame * L.units_per_frame));
+  // by value: kept in scalar registers instead of being re-read from memory
+  // after every global store (the compiler cannot rule out aliasing)
+  S = load_const(L.streams + U.stream);
+  const cband_t hb = (cband_t)S.hb;
+  const cband_t vb = (cband_t)S.vb;
+  const AOL_CONST uint64_t* table = (const AOL_CONST uint64_t*)L.ptr_table;
+  const uint64_t pin = table ? table[2 * S.ptr] : (uint64_t)L.ptrs[2 * S.ptr];
+  const uint64_t pout = table ? table[2 * S.ptr + 1] : (uint64_t)L.ptrs[2 * S.ptr + 1];
+  const int64_t fin = L.ptr_table ? 0 : L.fstride[2 * S.ptr];
+  const int64_t fout = L.ptr_table ? 0 : L.fstride[2 * S.ptr + 1];
+  G.src = (gsrc_t)pin + (int64_t)frame * fin * ES;
+  G.dst = (gdst_t)pout + (int64_t)frame * fout * (ELEM == kU8 ? 1 : 4);
+  const int R0x = U.xb * S.xreps, R0y = U.sy * S.seg;
+  const int nRx = min(S.xreps, S.rx - R0x);
+  const int nRy = min(S.seg, S.ry - R0y);
+  G.Lz = vb->q * (nRy - 1) + vb->span;
+  G.zrow0 = vb->q * R0y + vb->s_min;
+  G.M = (G.Lz + 15) >> 4;
+  G.NBV = (vb->p * nRy + 15) >> 4;
+  G.a0 = hb->q * R0x + hb->s_min - hb->delta;
+  G.orow0 = vb->p * R0y;
+  G.ocol0 = hb->p * R0x;
+  G.row_end = min(S.mh, G.orow0 + vb->p * nRy);
+  G.col_end = min(S.mw, G.ocol0 + hb->p * nRx);
+  G.nbh = (hb->p * nRx + 15) >> 4;
+  G.vec_in = S.vec_in && L.aligned;
+  G.vec_out = S.vec_out && L.aligned;
+}
 
 template <int ELEM, int SLOTS, bool SPLIT>
 __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
   constexpr int ES = ELEM == kU8 ? 1 : 2;
   constexpr int E = 16 / ES;
   constexpr bool split = (ELEM == kU8) && SPLIT;
+  constexpr int NW = (kBandThreads - kBandLoadThreads) / 64;  // compute waves
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool loader = wave < kBandLoadThreads / 64;
+  const int cw = wave - kBandLoadThreads / 64;  // compute wave index
+  const int ctid = tid - kBandLoadThreads;
   const int g = lane >> 4, n = lane & 15;
 
-  BandStager<ELEM, SLOTS> s0, s1;
-  const AxisBand* cur_hb = nullptr;
+  // The two roles loop over the same units separately, so that the loading
+  // waves' code never has a store in flight.
+  if (loader) {
+    for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
+      BandStream S;
+      BandUnitGeo G;
+      band_unit<ELEM>(L, u, S, G);
+      uint8_t* xs = lds + S.lds_x;
+      BandFeed<ELEM, SLOTS> F;
+      F.setup(S, G, tid);
+      if (G.vec_in) band_feed_unit<ELEM, SLOTS>(F, S, G, xs);
+      else band_feed_unit_gathered<ELEM, SLOTS>(F, S, G, xs);
+    }
+    return;
+  }
+
+  cband_t cur_hb = nullptr;
   for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
-    const int frame = u / L.units_per_frame;
-    const BandUnit U = L.units[u - frame * L.units_per_frame];
-    // by value: kept in scalar registers instead of being re-read from memory
-    // after every global store (the compiler cannot rule out aliasing)
-    const BandStream S = L.streams[U.stream];
-    const AxisBand* __restrict__ hb = S.hb;
-    const AxisBand* __restrict__ vb = S.vb;
+    BandStream S;
+    BandUnitGeo G;
+    band_unit<ELEM>(L, u, S, G);
+    const cband_t hb = (cband_t)S.hb;
+    const cband_t vb = (cband_t)S.vb;
     uint8_t* xs = lds + S.lds_x;
     uint8_t* zs = lds + S.lds_z;
     const v4i* fh = reinterpret_cast<const v4i*>(lds + S.lds_fh);
@@ -202,55 +375,35 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
     const int* bv = reinterpret_cast<const int*>(lds + S.lds_bv);
     const int RM = S.ring - 1;
 
-    lds_barrier();  // the previous unit is done with LDS
+    // Every unit ends with a barrier after the last reads of its LDS, so the
+    // next unit may overwrite any of it before its first barrier.
     if (hb != cur_hb) {  // coefficient operands and biases of this stream's filter
       cur_hb = hb;
-      const v4i* gh = reinterpret_cast<const v4i*>(S.hfrag);
-      const v4i* gv = reinterpret_cast<const v4i*>(S.vfrag);
-      for (int i = tid; i < hb->nfrag * 64; i += kBandThreads) const_cast<v4i*>(fh)[i] = gh[i];
-      for (int i = tid; i < vb->nfrag * 64; i += kBandThreads) const_cast<v4i*>(fv)[i] = gv[i];
+      const AOL_GLOBAL v4i* gh = (const AOL_GLOBAL v4i*)S.hfrag;
+      const AOL_GLOBAL v4i* gv = (const AOL_GLOBAL v4i*)S.vfrag;
+      for (int i = ctid; i < hb->nfrag * 64; i += NW * 64) const_cast<v4i*>(fh)[i] = gh[i];
+      for (int i = ctid; i < vb->nfrag * 64; i += NW * 64) const_cast<v4i*>(fv)[i] = gv[i];
       if constexpr (ELEM == kU8) {
-        for (int i = tid; i < hb->nblk * 16; i += kBandThreads) const_cast<int*>(bh)[i] = hb->bias[i];
-        for (int i = tid; i < vb->nblk * 16; i += kBandThreads) const_cast<int*>(bv)[i] = vb->bias[i];
+        for (int i = ctid; i < hb->nblk * 16; i += NW * 64) const_cast<int*>(bh)[i] = hb->bias[i];
+        for (int i = ctid; i < vb->nblk * 16; i += NW * 64) const_cast<int*>(bv)[i] = vb->bias[i];
       }
     }
-
-    BandUnitGeo G;
-    {
-      const void* pin = L.ptr_table ? L.ptr_table[2 * S.ptr] : L.ptrs[2 * S.ptr];
-      void* pout = L.ptr_table ? L.ptr_table[2 * S.ptr + 1] : const_cast<void*>(L.ptrs[2 * S.ptr + 1]);
-      const int64_t fin = L.ptr_table ? 0 : L.fstride[2 * S.ptr];
-      const int64_t fout = L.ptr_table ? 0 : L.fstride[2 * S.ptr + 1];
-      G.src = reinterpret_cast<const uint8_t*>(pin) + (int64_t)frame * fin * ES;
-      G.dst = reinterpret_cast<uint8_t*>(pout) + (int64_t)frame * fout * (ELEM == kU8 ? 1 : 4);
-      const int R0x = U.xb * S.xreps, R0y = U.sy * S.seg;
-      const int nRx = min(S.xreps, S.rx - R0x);
-      const int nRy = min(S.seg, S.ry - R0y);
-      G.Lz = vb->q * (nRy - 1) + vb->span;
-      G.zrow0 = vb->q * R0y + vb->s_min;
-      G.M = (G.Lz + 15) >> 4;
-      G.NBV = (vb->p * nRy + 15) >> 4;
-      G.a0 = hb->q * R0x + hb->s_min - hb->delta;
-      G.orow0 = vb->p * R0y;
-      G.ocol0 = hb->p * R0x;
-      G.row_end = min(S.mh, G.orow0 + vb->p * nRy);
-      G.col_end = min(S.mw, G.ocol0 + hb->p * nRx);
-      G.nbh = (hb->p * nRx + 15) >> 4;
-      G.vec_in = S.vec_in && L.aligned;
-      G.vec_out = S.vec_out && L.aligned;
+    if constexpr (ELEM != kU8) {
+      // float ring starts at zero so the zero taps of a block's padding never meet a NaN
+      for (int i = ctid; i < (S.nbh * 16 * S.rpitch) / 16; i += NW * 64) {
+        reinterpret_cast<v4i*>(zs)[i] = v4i{0, 0, 0, 0};
+        reinterpret_cast<v4i*>(zs + S.zhalf)[i] = v4i{0, 0, 0, 0};
+      }
     }
+    lds_barrier();  // step 0 staged, coefficients in place
 
-    // loads run AHEAD steps ahead: two stagers alternate (narrow lines), or
-    // one stager is issued at the start of a step and committed in its middle
-    constexpr int AHEAD = SLOTS <= 2 ? 2 : 1;
     int B = 0;  // next vertical block
-    auto step = [&](int m, BandStager<ELEM, SLOTS>& mine, BandStager<ELEM, SLOTS>& other) {
-      if (m + AHEAD < G.M) mine.issue(S, G, m + AHEAD, tid);
+    for (int m = 0; m < G.M; ++m) {
       // ---- horizontal pass: 16 intermediate lines of every 16-column block
-      if constexpr (ELEM == kU8 && !split && SLOTS <= 2) {
+      if constexpr (ELEM == kU8 && !split) {
         // two blocks per iteration: their LDS reads and MFMAs overlap
-        for (int b0 = wave; b0 < G.nbh; b0 += 2 * kBandWaves) {
-          const int b1 = b0 + kBandWaves;
+        for (int b0 = cw; b0 < G.nbh; b0 += 2 * NW) {
+          const int b1 = b0 + NW;
           const bool two = b1 < G.nbh;
           const int per0 = b0 / hb->nblk, lb0 = b0 - per0 * hb->nblk;
           const int per1 = two ? b1 / hb->nblk : per0, lb1 = two ? b1 - per1 * hb->nblk : lb0;
@@ -272,7 +425,7 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
           if (two) *reinterpret_cast<uint32_t*>(zs + (16 * b1 + n) * S.rpitch + zoff) = b_quant4(acc1, bh[lb1 * 16 + n]);
         }
       } else
-      for (int b = wave; b < G.nbh; b += kBandWaves) {
+      for (int b = cw; b < G.nbh; b += NW) {
         const int per = b / hb->nblk, lb = b - per * hb->nblk;
         const int c0 = hb->chunk0[lb] + per * (hb->q * 16 / E);  // a period is 16q elements
         const int nk = hb->nk[lb], fb = hb->frag[lb];
@@ -281,14 +434,10 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
           v4i acc = {0, 0, 0, 0}, acch = {0, 0, 0, 0};
           for (int kb = 0; kb < nk; ++kb) {
             const v4i av = b_to_i8(*reinterpret_cast<const v4i*>(xr + (c0 + 4 * kb + g) * 16));
-            if constexpr (split) {
-              acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, fh[((fb + kb) * 2) * 64 + lane], acc, 0, 0, 0);
-              acch = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, fh[((fb + kb) * 2 + 1) * 64 + lane], acch, 0, 0, 0);
-            } else {
-              acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, fh[(fb + kb) * 64 + lane], acc, 0, 0, 0);
-            }
+            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, fh[((fb + kb) * 2) * 64 + lane], acc, 0, 0, 0);
+            acch = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, fh[((fb + kb) * 2 + 1) * 64 + lane], acch, 0, 0, 0);
           }
-          if constexpr (split) acc = acc + acch * 128;
+          acc = acc + acch * 128;
           *reinterpret_cast<uint32_t*>(zs + (16 * b + n) * S.rpitch + ((16 * m + 4 * g) & RM)) =
               b_quant4(acc, bh[lb * 16 + n]);
         } else {
@@ -306,7 +455,6 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
         }
       }
       lds_barrier();  // staging consumed, intermediate lines written
-      if (m + 1 < G.M) other.commit(S, xs, tid);
       // ---- vertical blocks whose window is complete
       const int have = min(G.Lz, 16 * (m + 1));
       while (B < G.NBV) {
@@ -316,7 +464,7 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
         const int c0 = vb->chunk0[lb] + per * (vb->q * 16 / E);  // chunks of E intermediate lines
         const int nk = vb->nk[lb], fb = vb->frag[lb];
         const int orow = G.orow0 + 16 * B + n;
-        for (int cb = wave; cb < G.nbh; cb += kBandWaves) {
+        for (int cb = cw; cb < G.nbh; cb += NW) {
           const uint8_t* zr = zs + (16 * cb + n) * S.rpitch;
           const int col = G.ocol0 + 16 * cb + 4 * g;
           if constexpr (ELEM == kU8) {
@@ -333,9 +481,9 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
             if constexpr (split) acc = acc + acch * 128;
             if (orow < G.row_end) {
               const uint32_t y4 = b_quant4(acc, bv[lb * 16 + n]);
-              uint8_t* op = G.dst + (int64_t)orow * S.out_pitch + col;
+              gdst_t op = G.dst + (int64_t)orow * S.out_pitch + col;
               if (G.vec_out && col + 4 <= G.col_end) {
-                *reinterpret_cast<uint32_t*>(op) = y4;
+                *(AOL_GLOBAL uint32_t*)op = y4;
               } else {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
@@ -351,9 +499,9 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
               acc = b_mfma16<ELEM>(*reinterpret_cast<const v4i*>(zr + S.zhalf + off), bf, acc);
             }
             if (orow < G.row_end) {
-              float* op = reinterpret_cast<float*>(G.dst) + (int64_t)orow * S.out_pitch + col;
+              AOL_GLOBAL float* op = (AOL_GLOBAL float*)G.dst + (int64_t)orow * S.out_pitch + col;
               if (G.vec_out && col + 4 <= G.col_end) {
-                *reinterpret_cast<v4f*>(op) = acc;
+                *(AOL_GLOBAL v4f*)op = acc;
               } else {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
@@ -364,43 +512,25 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
         }
         ++B;
       }
-      lds_barrier();  // ring reads of this step done, next staging committed
-    };
-
-    if constexpr (ELEM != kU8) {
-      // float ring starts at zero so the zero taps of a block's padding never meet a NaN
-      for (int i = tid; i < (S.nbh * 16 * S.rpitch) / 16; i += kBandThreads) {
-        reinterpret_cast<v4i*>(zs)[i] = v4i{0, 0, 0, 0};
-        reinterpret_cast<v4i*>(zs + S.zhalf)[i] = v4i{0, 0, 0, 0};
-      }
-    }
-    s0.issue(S, G, 0, tid);
-    if (AHEAD == 2 && G.M > 1) s1.issue(S, G, 1, tid);
-    s0.commit(S, xs, tid);
-    lds_barrier();
-    if constexpr (AHEAD == 2) {
-      for (int m = 0; m < G.M; m += 2) {
-        step(m, s0, s1);
-        if (m + 1 < G.M) step(m + 1, s1, s0);
-      }
-    } else {
-      for (int m = 0; m < G.M; ++m) step(m, s0, s0);
+      lds_barrier();  // ring reads of this step done, step m+1 staged
     }
   }
 }
 
 using BandFn = void (*)(BandLaunch);
 
-template <int ELEM>
-static BandFn band_pick_e(int slots, bool split) {
-  if (slots <= 2) return split ? k_band<ELEM, 2, true> : k_band<ELEM, 2, false>;
-  return split ? k_band<ELEM, 4, true> : k_band<ELEM, 4, false>;
+template <int ELEM, bool SPLIT>
+static BandFn band_pick_s(int slots) {
+  if (slots <= 1) return k_band<ELEM, 1, SPLIT>;
+  if (slots <= 2) return k_band<ELEM, 2, SPLIT>;
+  if (slots <= 4) return k_band<ELEM, 4, SPLIT>;
+  return k_band<ELEM, 8, SPLIT>;
 }
 
 static BandFn band_pick(int elem, int slots, bool split) {
-  if (elem == kU8) return band_pick_e<kU8>(slots, split);
-  if (elem == kBF16) return band_pick_e<kBF16>(slots, false);
-  return band_pick_e<kFP16>(slots, false);
+  if (elem == kU8) return split ? band_pick_s<kU8, true>(slots) : band_pick_s<kU8, false>(slots);
+  if (elem == kBF16) return band_pick_s<kBF16, false>(slots);
+  return band_pick_s<kFP16, false>(slots);
 }
 
 hipError_t band_prepare(int elem, int slots, bool split, size_t lds_bytes, int* wg_per_cu) {

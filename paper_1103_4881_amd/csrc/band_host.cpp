@@ -84,7 +84,8 @@ aol_status build_band_stream(const FilterBands& fb, int64_t h, int64_t w, int64_
     BandStream T;
     memset(&T, 0, sizeof T);
     total = layout(fb, nbh, nch, T);
-    if (total <= lds_budget || xreps > 0 || xr <= 16) {
+    const bool fits = total <= lds_budget && 16 * nch <= kBandMaxSlots * kBandLoadThreads;
+    if (fits || xreps > 0 || xr <= 16) {
       S = T;
       break;
     }
@@ -93,8 +94,8 @@ aol_status build_band_stream(const FilterBands& fb, int64_t h, int64_t w, int64_
     xr = 16 * std::max(1, (periods + 1) / 2);
   }
   if (total > lds_budget) return fail(AOL_ERR_UNSUPPORTED, "a column band of %d repetitions needs %d bytes of LDS", xr, total);
-  const int sl = (16 * nch + kBandThreads - 1) / kBandThreads;
-  if (sl > 4) return fail(AOL_ERR_UNSUPPORTED, "band lines of %d chunks exceed the staging slots", nch);
+  const int sl = (16 * nch + kBandLoadThreads - 1) / kBandLoadThreads;
+  if (sl > kBandMaxSlots) return fail(AOL_ERR_UNSUPPORTED, "band lines of %d chunks exceed the staging slots", nch);
   S.h = (int32_t)h;
   S.w = (int32_t)w;
   S.mh = (int32_t)(vb.p * ry);
