@@ -34,8 +34,10 @@ struct alignas(16) AxisBand {
   int32_t chunk_elems;      // elements per 16-byte chunk (16 for u8, 8 for 16-bit)
   int32_t nchunks;          // chunks touched by any K-step of a full tile
   int32_t split;            // u8: coefficients carried as lo + 128*hi operands
-  int32_t nfrag;            // fragments (64 lanes x 16 B) of the whole band
-  int32_t pad0, pad1, pad2;
+  int32_t nfrag;            // fragments (64 lanes x 16 B) of the whole band, the zero one included
+  int32_t zfrag;            // K-step index of an all-zero fragment (after the others)
+  int32_t kmax;             // largest nk of the band
+  int32_t pad2;
   int32_t chunk0[kMaxNB];   // first chunk of block b's window
   int32_t nk[kMaxNB];       // K-steps (4 chunks each) of block b
   int32_t frag[kMaxNB];     // first fragment of block b (64 lanes x 16 B each)
@@ -103,10 +105,10 @@ struct BandStream {
   int32_t nch;             // 16-byte chunks staged per input line of a full band
   uint32_t nch_magic;      // ceil(2^32 / nch)
   int32_t seg;             // repetitions per segment (multiple of 16)
-  int32_t ring;            // intermediate lines kept (power of two)
+  int32_t ring;            // intermediate lines kept (a multiple of 16)
   int32_t rpitch;          // bytes between rows of the ring (of each half for the float form)
   int32_t zhalf;           // float form: bytes from the hi ring to the lo ring
-  int32_t xpitch;          // bytes between staged lines
+  int32_t xpitch;          // bytes between staged lines (two buffers of 16 lines)
   int32_t lds_x, lds_z, lds_fh, lds_fv, lds_bh, lds_bv;  // LDS byte offsets
   int32_t vec_in;          // line length a multiple of one chunk and pitch chunk aligned
   int32_t vec_out;         // output pitch a multiple of 4 elements

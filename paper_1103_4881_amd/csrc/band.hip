@@ -60,6 +60,8 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 
+constexpr int kBandWaves = kBandThreads / 64;
+
 // Pointers read from memory (descriptor and pointer tables) are generic to
 // the compiler, and generic accesses become flat instructions, which count
 // against both the vector-memory and the LDS counters: every wait for LDS
@@ -179,9 +181,9 @@ template <int ELEM, int SLOTS>
 struct BandFeed {
   static constexpr int ES = ELEM == kU8 ? 1 : 2;
   static constexpr int E = 16 / ES;
-  int r[SLOTS];    // line of the step
-  int col[SLOTS];  // first element of the chunk, wrapped into the line
-  int xo[SLOTS];   // LDS byte offset of the chunk in the staging lines
+  gsrc_t base[SLOTS];  // the chunk's column in the plane's line 0
+  int row[SLOTS];      // plane line of the chunk in step 0, before the wrap
+  int xo[SLOTS];       // LDS byte offset of the chunk in the staging lines
 
   __device__ __forceinline__ void setup(const BandStream& S, const BandUnitGeo& G, int ltid) {
 #pragma unroll
@@ -194,29 +196,38 @@ struct BandFeed {
       // which would leave its register's load outstanding on the other path
       if (rr >= 16) { rr = 15; c = 0; }
       xo[s] = rr * S.xpitch + c * 16;
-      r[s] = rr;
+      row[s] = G.zrow0 + rr;
       int cl = G.a0 + c * E;
       if (cl < 0 || cl >= S.w) cl = bpmod(cl, S.w);
-      col[s] = cl;
+      base[s] = G.src + (int64_t)cl * ES;
     }
   }
 
   __device__ __forceinline__ gsrc_t line(const BandStream& S, const BandUnitGeo& G, int m, int s) const {
-    const int l = min(16 * m + r[s], G.Lz - 1);
-    int grow = G.zrow0 + l;
-    if (grow < 0 || grow >= S.h) grow = bpmod(grow, S.h);
+    const int grow = bpmod(min(row[s] + 16 * m, G.zrow0 + G.Lz - 1), S.h);
     return G.src + (int64_t)grow * S.in_pitch * ES;
   }
 
   // Whole chunks of a circular line (a wrapped chunk is another chunk).
   // Straight-line code with the same loads on every path, so the compiler's
   // count of loads in flight stays exact: rows are clamped and wrapped with
-  // arithmetic, and a step past the unit loads its last line again.
+  // arithmetic, and a step past the unit loads its last line again. WRAP1:
+  // the unit's lines lie within one plane height of the plane, so one
+  // conditional add or subtract wraps them.
+  template <bool WRAP1>
   __device__ __forceinline__ void issue(v4i (&pre)[SLOTS], const BandStream& S, const BandUnitGeo& G, int m) const {
+    const int last = G.zrow0 + G.Lz - 1;
+    const uint32_t pitch = (uint32_t)(S.in_pitch * ES);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-      const int grow = bpmod(G.zrow0 + min(16 * m + r[s], G.Lz - 1), S.h);
-      pre[s] = *(const AOL_GLOBAL v4i*)(G.src + ((int64_t)grow * S.in_pitch + col[s]) * ES);
+      int gr = min(row[s] + 16 * m, last);
+      if constexpr (WRAP1) {
+        gr = gr < 0 ? gr + S.h : gr;
+        gr = gr >= S.h ? gr - S.h : gr;
+      } else {
+        gr = bpmod(gr, S.h);
+      }
+      pre[s] = *(const AOL_GLOBAL v4i*)(base[s] + (uint64_t)(uint32_t)gr * pitch);
     }
   }
 
@@ -226,72 +237,199 @@ struct BandFeed {
   __device__ __forceinline__ void stage_gathered(const BandStream& S, const BandUnitGeo& G, int m, uint8_t* xs) const {
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-      const v4i a = b_load_chunk_wrap<ES>(line(S, G, m, s), col[s], S.w);
-      *reinterpret_cast<v4i*>(xs + xo[s]) = a;
+      const int col = (int)((base[s] - G.src) / ES);
+      const v4i a = b_load_chunk_wrap<ES>(line(S, G, m, s), col, S.w);
+      *reinterpret_cast<v4i*>(xs + xo[s]) = ELEM == kU8 ? b_to_i8(a) : a;
     }
   }
 
+  // integer form: staged as signed bytes x - 128 (the matrix-core operand)
   __device__ __forceinline__ void commit(const v4i (&pre)[SLOTS], uint8_t* xs) const {
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) *reinterpret_cast<v4i*>(xs + xo[s]) = pre[s];
+    for (int s = 0; s < SLOTS; ++s)
+      *reinterpret_cast<v4i*>(xs + xo[s]) = ELEM == kU8 ? b_to_i8(pre[s]) : pre[s];
+  }
+};
+
+// Horizontal-pass block table of one wave for one unit: lane i describes
+// the wave's i-th block (w + 16*i), read back with readlane.
+// Bits 0-15: byte offset of the block's first chunk in a staged line;
+// 16-23: first coefficient fragment; 24-28: block within the period; 29-31:
+// K-steps.
+__device__ __forceinline__ uint32_t hblock_entry(cband_t hb, int b, int E) {
+  const int per = b / hb->nblk, lb = b - per * hb->nblk;
+  const int c0 = hb->chunk0[lb] + per * (hb->q * 16 / E);  // a period is 16q elements
+  return (uint32_t)(c0 * 16) | ((uint32_t)hb->frag[lb] << 16) | ((uint32_t)lb << 24) | ((uint32_t)hb->nk[lb] << 29);
+}
+
+// One horizontal block's operands: KM K-steps of A (16 staged lines x 4
+// chunks) and B (coefficients); steps past the block's own nk read its first
+// chunk against the zero fragment.
+template <int ELEM, bool SPLIT, int KM>
+struct HOps {
+  v4i a[KM], b[KM], bh[SPLIT ? KM : 1];
+  int bias, nk;
+  __device__ __forceinline__ void load(uint32_t t, const uint8_t* xl, const uint8_t* fl, const uint8_t* bl, int zfrag) {
+    const int c0 = (int)(t & 0xFFFFu), fb = (int)((t >> 16) & 0xFFu), lb = (int)((t >> 24) & 31u);
+    nk = (int)(t >> 29);
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      const bool on = k < nk;
+      a[k] = *reinterpret_cast<const v4i*>(xl + (on ? c0 + 64 * k : c0));
+      const int f = on ? fb + k : zfrag;
+      if constexpr (SPLIT) {
+        b[k] = *reinterpret_cast<const v4i*>(fl + (2 * f) * 1024);
+        bh[k] = *reinterpret_cast<const v4i*>(fl + (2 * f + 1) * 1024);
+      } else {
+        b[k] = *reinterpret_cast<const v4i*>(fl + f * 1024);
+      }
+    }
+    if constexpr (ELEM == kU8) bias = *reinterpret_cast<const int*>(bl + lb * 64);
+  }
+};
+
+// Horizontal pass of one step by one wave (every wave of the workgroup
+// takes part: blocks w, w + 16, ...): 16 intermediate lines of each of its
+// 16-column blocks, written transposed into the ring.
+template <int ELEM, bool SPLIT, int KM, int NB>  // NB: blocks per iteration (operands in flight)
+struct BandH {
+  static constexpr int ES = ELEM == kU8 ? 1 : 2;
+  static constexpr int E = 16 / ES;
+  uint32_t tbl;
+  int nbi, hz, xbuf, zstep, zhalf;
+  const uint8_t* xl;   // lane's staged line and chunk of a K-step (buffer 0)
+  const uint8_t* fhl;  // lane's slot of a coefficient fragment
+  const uint8_t* bhl;  // lane's bias of block 0 of a period
+  uint8_t* zl;         // lane's ring row of the wave's first block
+
+  __device__ __forceinline__ void setup(const BandStream& S, const BandUnitGeo& G, const uint8_t* lds, int w,
+                                        int lane) {
+    const cband_t hb = (cband_t)S.hb;
+    const int g = lane >> 4, n = lane & 15;
+    nbi = w < G.nbh ? (G.nbh - w + kBandWaves - 1) / kBandWaves : 0;
+    tbl = lane < nbi ? hblock_entry(hb, w + kBandWaves * lane, E) : 0u;
+    hz = hb->zfrag;
+    xbuf = 16 * S.xpitch;
+    zstep = 16 * kBandWaves * S.rpitch;
+    zhalf = S.zhalf;
+    xl = lds + S.lds_x + n * S.xpitch + g * 16;
+    fhl = lds + S.lds_fh + lane * 16;
+    bhl = lds + S.lds_bh + n * 4;
+    zl = const_cast<uint8_t*>(lds) + S.lds_z + (16 * w + n) * S.rpitch;
+  }
+
+  // zm: ring line of step m's first intermediate line
+  __device__ __forceinline__ void run(int m, int zm, int g) const {
+    const uint8_t* xm = xl + (m & 1) * xbuf;
+    uint8_t* zrow = zl + (zm + 4 * g) * ES;  // lane's 4 intermediate lines in its ring row
+    for (int i = 0; i < nbi; i += NB) {
+      HOps<ELEM, SPLIT, KM> op[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int ii = min(i + j, nbi - 1);  // a missing block repeats the last one
+        op[j].load(__builtin_amdgcn_readlane(tbl, ii), xm, fhl, bhl, hz);
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j > 0 && i + j >= nbi) break;
+        uint8_t* zp = zrow + (i + j) * zstep;
+        if constexpr (ELEM == kU8) {
+          v4i acc = {op[j].bias, op[j].bias, op[j].bias, op[j].bias}, acch = {0, 0, 0, 0};
+#pragma unroll
+          for (int k = 0; k < KM; ++k) {
+            if (k > 0 && k >= op[j].nk) break;  // uniform: the block's own K-steps only
+            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(op[j].a[k], op[j].b[k], acc, 0, 0, 0);
+            if constexpr (SPLIT) acch = __builtin_amdgcn_mfma_i32_16x16x64_i8(op[j].a[k], op[j].bh[k], acch, 0, 0, 0);
+          }
+          if constexpr (SPLIT) acc = acc + acch * 128;
+          // kept as signed bytes z - 128, the vertical pass's operand
+          *reinterpret_cast<uint32_t*>(zp) = b_quant4(acc, 0) ^ 0x80808080u;
+        } else {
+          v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int k = 0; k < KM; ++k) {
+            if (k > 0 && k >= op[j].nk) break;
+            acc = b_mfma16<ELEM>(op[j].a[k], op[j].b[k], acc);
+          }
+          // hi/lo pair: hi = round(z), lo = round(z - hi)
+          const uint32_t h01 = b_pack2<ELEM>(acc[0], acc[1]);
+          const uint32_t h23 = b_pack2<ELEM>(acc[2], acc[3]);
+          const uint32_t l01 = b_pack2<ELEM>(acc[0] - b_lo16<ELEM>(h01), acc[1] - b_hi16<ELEM>(h01));
+          const uint32_t l23 = b_pack2<ELEM>(acc[2] - b_lo16<ELEM>(h23), acc[3] - b_hi16<ELEM>(h23));
+          *reinterpret_cast<uint2*>(zp) = uint2{h01, h23};
+          *reinterpret_cast<uint2*>(zp + zhalf) = uint2{l01, l23};
+        }
+      }
+    }
   }
 };
 
 // Loading waves of one unit: keep D steps of input lines in flight in
-// registers and commit step m+1 into the staging lines while the compute
-// waves run the vertical pass of step m. These waves issue no stores to
-// memory, so their waits on loads count exactly (on gfx9 a wave with loads
-// and stores outstanding can only wait for all of them).
-template <int ELEM, int SLOTS>
+// registers and commit step m+1 into its staging buffer while the compute
+// waves work on step m (from the other buffer); one barrier per step, one at
+// the start (step 0 staged) and one at the end (the unit's LDS free). These
+// waves issue no stores to memory, so their waits on loads count exactly (on
+// gfx9 a wave with loads and stores outstanding can only wait for all of
+// them).
+template <int ELEM, int SLOTS, bool WRAP1, class HP>
 __device__ __forceinline__ void band_feed_unit(const BandFeed<ELEM, SLOTS>& F, const BandStream& S,
-                                               const BandUnitGeo& G, uint8_t* xs) {
+                                               const BandUnitGeo& G, uint8_t* xs, const HP& H, int g) {
   constexpr int D = BandDepth<SLOTS>::value;
+  const int xbuf = 16 * S.xpitch;  // bytes from staging buffer 0 to buffer 1
   v4i pre[D][SLOTS];
 #pragma unroll
-  for (int k = 0; k < D; ++k) F.issue(pre[k], S, G, k);
+  for (int k = 0; k < D; ++k) F.template issue<WRAP1>(pre[k], S, G, k);
   F.commit(pre[0], xs);
-  F.issue(pre[0], S, G, D);
+  F.template issue<WRAP1>(pre[0], S, G, D);
   lds_barrier();  // step 0 staged
   // Every iteration commits and re-issues one register set, so the loads in
   // flight at the loop head are the same sets in the same order on entry and
-  // on the back edge. Steps past the unit stage its last line again into
-  // staging lines nobody reads any more.
-  // The loop runs whole groups of D steps, without an exit in between (an
-  // exit path would reach the loop head with other loads in flight).
-  int m0 = 0;
+  // on the back edge. Steps past the unit stage its last line again into a
+  // buffer nobody reads any more. The loop runs whole groups of D steps,
+  // without an exit in between (an exit path would reach the loop head with
+  // other loads in flight).
+  int m0 = 0, zm = 0;
   for (; m0 + D <= G.M; m0 += D) {
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      lds_barrier();  // horizontal pass of step m0+k done with the staging lines
+      const int m = m0 + k;
       const int j = (k + 1) % D;  // a constant once the loop is unrolled
-      F.commit(pre[j], xs);
-      F.issue(pre[j], S, G, m0 + k + 1 + D);
-      lds_barrier();  // step m0+k+1 staged
+      F.commit(pre[j], xs + ((m + 1) & 1) * xbuf);
+      F.template issue<WRAP1>(pre[j], S, G, m + 1 + D);
+      H.run(m, zm, g);  // this wave's share of step m's horizontal pass
+      zm = zm + 16 == S.ring ? 0 : zm + 16;
+      lds_barrier();  // step m done with its buffer, step m+1 staged
     }
   }
 #pragma unroll
   for (int k = 0; k + 1 < D; ++k) {
     if (m0 + k < G.M) {
-      lds_barrier();
-      F.commit(pre[(k + 1) % D], xs);
+      F.commit(pre[(k + 1) % D], xs + ((m0 + k + 1) & 1) * xbuf);
+      H.run(m0 + k, zm, g);
+      zm = zm + 16 == S.ring ? 0 : zm + 16;
       lds_barrier();
     }
   }
   // nothing of this unit stays in flight into the next one
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  lds_barrier();  // the compute waves are done with the unit's LDS
 }
 
 // The same for lines that are gathered element by element: no prefetch.
-template <int ELEM, int SLOTS>
+template <int ELEM, int SLOTS, class HP>
 __device__ __forceinline__ void band_feed_unit_gathered(const BandFeed<ELEM, SLOTS>& F, const BandStream& S,
-                                                                  const BandUnitGeo& G, uint8_t* xs) {
+                                                        const BandUnitGeo& G, uint8_t* xs, const HP& H, int g) {
+  const int xbuf = 16 * S.xpitch;
   F.stage_gathered(S, G, 0, xs);
   lds_barrier();  // step 0 staged
+  int zm = 0;
   for (int m = 0; m < G.M; ++m) {
-    lds_barrier();  // horizontal pass of step m done with the staging lines
-    if (m + 1 < G.M) F.stage_gathered(S, G, m + 1, xs);
-    lds_barrier();  // step m+1 staged
+    if (m + 1 < G.M) F.stage_gathered(S, G, m + 1, xs + ((m + 1) & 1) * xbuf);
+    H.run(m, zm, g);
+    zm = zm + 16 == S.ring ? 0 : zm + 16;
+    lds_barrier();  // step m done with its buffer, step m+1 staged
   }
+  lds_barrier();  // the compute waves are done with the unit's LDS
 }
 
 // Stream descriptor and geometry of unit u (of the whole launch: units of
@@ -330,12 +468,28 @@ __device__ __forceinline__ void band_unit(const BandLaunch& L, int u, BandStream
   G.vec_out = S.vec_out && L.aligned;
 }
 
-template <int ELEM, int SLOTS, bool SPLIT>
+// Vertical block table of one unit: lane B describes vertical block B.
+// Entry: bits 0-15: ring line of its first chunk; 16-23: first
+// fragment; 24-28: block within the period; 29-31: K-steps. Need: the
+// intermediate lines (from the unit's first) its window reaches.
+__device__ __forceinline__ void vblock_entry(cband_t vb, int B, int E, int ring, int Lz, uint32_t& ent, int& need) {
+  const int per = B / vb->nblk, lb = B - per * vb->nblk;
+  const int c0 = vb->chunk0[lb] + per * (vb->q * 16 / E);  // chunks of E intermediate lines
+  ent = (uint32_t)((c0 * E) % ring) | ((uint32_t)vb->frag[lb] << 16) | ((uint32_t)lb << 24) |
+        ((uint32_t)vb->nk[lb] << 29);
+  need = min(Lz, vb->wend[lb] + 16 * per * vb->q);
+}
+
+// GATHER: an instance for launches with a line that is not made of whole
+// 16-byte chunks (its width or pitch, or a pointer), whose loading waves
+// gather elements; the other instances only stream whole chunks.
+template <int ELEM, int SLOTS, bool SPLIT, int KM, bool GATHER>
 __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
   constexpr int ES = ELEM == kU8 ? 1 : 2;
   constexpr int E = 16 / ES;
   constexpr bool split = (ELEM == kU8) && SPLIT;
   constexpr int NW = (kBandThreads - kBandLoadThreads) / 64;  // compute waves
+  constexpr int NB = KM <= 2 && !split ? 4 : 2;               // blocks per iteration (operands in flight)
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -354,8 +508,11 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
       uint8_t* xs = lds + S.lds_x;
       BandFeed<ELEM, SLOTS> F;
       F.setup(S, G, tid);
-      if (G.vec_in) band_feed_unit<ELEM, SLOTS>(F, S, G, xs);
-      else band_feed_unit_gathered<ELEM, SLOTS>(F, S, G, xs);
+      BandH<ELEM, split, KM, 1> H;  // one block at a time: the prefetch holds the registers
+      H.setup(S, G, lds, wave, lane);
+      if constexpr (GATHER) band_feed_unit_gathered<ELEM, SLOTS>(F, S, G, xs, H, g);
+      else if (G.zrow0 >= -S.h && G.zrow0 + G.Lz <= 2 * S.h) band_feed_unit<ELEM, SLOTS, true>(F, S, G, xs, H, g);
+      else band_feed_unit<ELEM, SLOTS, false>(F, S, G, xs, H, g);
     }
     return;
   }
@@ -369,11 +526,10 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
     const cband_t vb = (cband_t)S.vb;
     uint8_t* xs = lds + S.lds_x;
     uint8_t* zs = lds + S.lds_z;
-    const v4i* fh = reinterpret_cast<const v4i*>(lds + S.lds_fh);
-    const v4i* fv = reinterpret_cast<const v4i*>(lds + S.lds_fv);
-    const int* bh = reinterpret_cast<const int*>(lds + S.lds_bh);
-    const int* bv = reinterpret_cast<const int*>(lds + S.lds_bv);
-    const int RM = S.ring - 1;
+    const uint8_t* fh = lds + S.lds_fh;
+    const uint8_t* fv = lds + S.lds_fv;
+    const uint8_t* bh = lds + S.lds_bh;
+    const uint8_t* bv = lds + S.lds_bv;
 
     // Every unit ends with a barrier after the last reads of its LDS, so the
     // next unit may overwrite any of it before its first barrier.
@@ -381,11 +537,11 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
       cur_hb = hb;
       const AOL_GLOBAL v4i* gh = (const AOL_GLOBAL v4i*)S.hfrag;
       const AOL_GLOBAL v4i* gv = (const AOL_GLOBAL v4i*)S.vfrag;
-      for (int i = ctid; i < hb->nfrag * 64; i += NW * 64) const_cast<v4i*>(fh)[i] = gh[i];
-      for (int i = ctid; i < vb->nfrag * 64; i += NW * 64) const_cast<v4i*>(fv)[i] = gv[i];
+      for (int i = ctid; i < hb->nfrag * 64; i += NW * 64) ((v4i*)fh)[i] = gh[i];
+      for (int i = ctid; i < vb->nfrag * 64; i += NW * 64) ((v4i*)fv)[i] = gv[i];
       if constexpr (ELEM == kU8) {
-        for (int i = ctid; i < hb->nblk * 16; i += NW * 64) const_cast<int*>(bh)[i] = hb->bias[i];
-        for (int i = ctid; i < vb->nblk * 16; i += NW * 64) const_cast<int*>(bv)[i] = vb->bias[i];
+        for (int i = ctid; i < hb->nblk * 16; i += NW * 64) ((int*)bh)[i] = hb->bias[i];
+        for (int i = ctid; i < vb->nblk * 16; i += NW * 64) ((int*)bv)[i] = vb->bias[i];
       }
     }
     if constexpr (ELEM != kU8) {
@@ -395,114 +551,92 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
         reinterpret_cast<v4i*>(zs + S.zhalf)[i] = v4i{0, 0, 0, 0};
       }
     }
-    lds_barrier();  // step 0 staged, coefficients in place
-
+    // this wave's share of the horizontal pass, and the unit's vertical
+    // blocks (lane B: block B)
+    BandH<ELEM, split, KM, NB> H;
+    H.setup(S, G, lds, wave, lane);
+    uint32_t vtbl = 0;
+    int vneed = 0;
+    if (lane < G.NBV) vblock_entry(vb, lane, E, S.ring, G.Lz, vtbl, vneed);
+    const int vz = vb->zfrag;
+    const uint8_t* fvl = fv + lane * 16;
     int B = 0;  // next vertical block
-    for (int m = 0; m < G.M; ++m) {
-      // ---- horizontal pass: 16 intermediate lines of every 16-column block
-      if constexpr (ELEM == kU8 && !split) {
-        // two blocks per iteration: their LDS reads and MFMAs overlap
-        for (int b0 = cw; b0 < G.nbh; b0 += 2 * NW) {
-          const int b1 = b0 + NW;
-          const bool two = b1 < G.nbh;
-          const int per0 = b0 / hb->nblk, lb0 = b0 - per0 * hb->nblk;
-          const int per1 = two ? b1 / hb->nblk : per0, lb1 = two ? b1 - per1 * hb->nblk : lb0;
-          const int c00 = hb->chunk0[lb0] + per0 * hb->q, c01 = hb->chunk0[lb1] + per1 * hb->q;
-          const int nk0 = hb->nk[lb0], nk1 = two ? hb->nk[lb1] : 0;
-          const int fb0 = hb->frag[lb0], fb1 = hb->frag[lb1];
-          const uint8_t* xr = xs + n * S.xpitch;
-          v4i acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-          const int nkm = nk0 > nk1 ? nk0 : nk1;
-          for (int kb = 0; kb < nkm; ++kb) {
-            v4i a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
-            if (kb < nk0) a0 = *reinterpret_cast<const v4i*>(xr + (c00 + 4 * kb + g) * 16);
-            if (kb < nk1) a1 = *reinterpret_cast<const v4i*>(xr + (c01 + 4 * kb + g) * 16);
-            if (kb < nk0) acc0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(b_to_i8(a0), fh[(fb0 + kb) * 64 + lane], acc0, 0, 0, 0);
-            if (kb < nk1) acc1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(b_to_i8(a1), fh[(fb1 + kb) * 64 + lane], acc1, 0, 0, 0);
+    int needB = __builtin_amdgcn_readlane(vneed, 0);
+
+    // ---- vertical blocks whose window lies in the first `have` intermediate lines
+    auto vpass = [&](int have) {
+      while (B < G.NBV && needB <= have) {
+        const uint32_t t = __builtin_amdgcn_readlane(vtbl, B);
+        const int c0 = (int)(t & 0xFFFFu), fb = (int)((t >> 16) & 0xFFu), lb = (int)((t >> 24) & 31u);
+        const int nk = (int)(t >> 29);
+        // this block's coefficient operands and ring offsets, for every column block
+        v4i bf[KM], bfh[split ? KM : 1];
+        int aoff[KM];
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          const bool on = k < nk;
+          const int f = on ? fb + k : vz;
+          if constexpr (split) {
+            bf[k] = *reinterpret_cast<const v4i*>(fvl + (2 * f) * 1024);
+            bfh[k] = *reinterpret_cast<const v4i*>(fvl + (2 * f + 1) * 1024);
+          } else {
+            bf[k] = *reinterpret_cast<const v4i*>(fvl + f * 1024);
           }
-          const int zoff = (16 * m + 4 * g) & RM;
-          *reinterpret_cast<uint32_t*>(zs + (16 * b0 + n) * S.rpitch + zoff) = b_quant4(acc0, bh[lb0 * 16 + n]);
-          if (two) *reinterpret_cast<uint32_t*>(zs + (16 * b1 + n) * S.rpitch + zoff) = b_quant4(acc1, bh[lb1 * 16 + n]);
+          aoff[k] = ((c0 + ((on ? 4 * k : 0) + g) * E) % S.ring) * ES;  // ring bytes of the lane's chunk
         }
-      } else
-      for (int b = cw; b < G.nbh; b += NW) {
-        const int per = b / hb->nblk, lb = b - per * hb->nblk;
-        const int c0 = hb->chunk0[lb] + per * (hb->q * 16 / E);  // a period is 16q elements
-        const int nk = hb->nk[lb], fb = hb->frag[lb];
-        const uint8_t* xr = xs + n * S.xpitch;
-        if constexpr (ELEM == kU8) {
-          v4i acc = {0, 0, 0, 0}, acch = {0, 0, 0, 0};
-          for (int kb = 0; kb < nk; ++kb) {
-            const v4i av = b_to_i8(*reinterpret_cast<const v4i*>(xr + (c0 + 4 * kb + g) * 16));
-            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, fh[((fb + kb) * 2) * 64 + lane], acc, 0, 0, 0);
-            acch = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, fh[((fb + kb) * 2 + 1) * 64 + lane], acch, 0, 0, 0);
-          }
-          acc = acc + acch * 128;
-          *reinterpret_cast<uint32_t*>(zs + (16 * b + n) * S.rpitch + ((16 * m + 4 * g) & RM)) =
-              b_quant4(acc, bh[lb * 16 + n]);
-        } else {
-          v4f acc = {0.f, 0.f, 0.f, 0.f};
-          for (int kb = 0; kb < nk; ++kb)
-            acc = b_mfma16<ELEM>(*reinterpret_cast<const v4i*>(xr + (c0 + 4 * kb + g) * 16), fh[(fb + kb) * 64 + lane], acc);
-          // hi/lo pair: hi = round(z), lo = round(z - hi)
-          const uint32_t h01 = b_pack2<ELEM>(acc[0], acc[1]);
-          const uint32_t h23 = b_pack2<ELEM>(acc[2], acc[3]);
-          const uint32_t l01 = b_pack2<ELEM>(acc[0] - b_lo16<ELEM>(h01), acc[1] - b_hi16<ELEM>(h01));
-          const uint32_t l23 = b_pack2<ELEM>(acc[2] - b_lo16<ELEM>(h23), acc[3] - b_hi16<ELEM>(h23));
-          uint8_t* zp = zs + (16 * b + n) * S.rpitch + ((16 * m + 4 * g) & RM) * 2;
-          *reinterpret_cast<uint2*>(zp) = uint2{h01, h23};
-          *reinterpret_cast<uint2*>(zp + S.zhalf) = uint2{l01, l23};
-        }
-      }
-      lds_barrier();  // staging consumed, intermediate lines written
-      // ---- vertical blocks whose window is complete
-      const int have = min(G.Lz, 16 * (m + 1));
-      while (B < G.NBV) {
-        const int per = B / vb->nblk, lb = B - per * vb->nblk;
-        const int need = min(G.Lz, vb->wend[lb] + 16 * per * vb->q);
-        if (need > have) break;
-        const int c0 = vb->chunk0[lb] + per * (vb->q * 16 / E);  // chunks of E intermediate lines
-        const int nk = vb->nk[lb], fb = vb->frag[lb];
+        const int bias = ELEM == kU8 ? *reinterpret_cast<const int*>(bv + lb * 64 + n * 4) : 0;
         const int orow = G.orow0 + 16 * B + n;
-        for (int cb = cw; cb < G.nbh; cb += NW) {
-          const uint8_t* zr = zs + (16 * cb + n) * S.rpitch;
-          const int col = G.ocol0 + 16 * cb + 4 * g;
-          if constexpr (ELEM == kU8) {
-            v4i acc = {0, 0, 0, 0}, acch = {0, 0, 0, 0};
-            for (int kb = 0; kb < nk; ++kb) {
-              const v4i av = b_to_i8(*reinterpret_cast<const v4i*>(zr + (((c0 + 4 * kb + g) * 16) & RM)));
-              if constexpr (split) {
-                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, fv[((fb + kb) * 2) * 64 + lane], acc, 0, 0, 0);
-                acch = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, fv[((fb + kb) * 2 + 1) * 64 + lane], acch, 0, 0, 0);
-              } else {
-                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, fv[(fb + kb) * 64 + lane], acc, 0, 0, 0);
-              }
+        const bool rows_in = G.vec_out && G.orow0 + 16 * B + 16 <= G.row_end;  // uniform
+        gdst_t rowp = G.dst + ((int64_t)orow * S.out_pitch + G.ocol0 + 4 * g) * (ELEM == kU8 ? 1 : 4);
+        for (int cb0 = cw; cb0 < G.nbh; cb0 += NB * NW) {
+          v4i a[NB][KM], al[NB][ELEM == kU8 ? 1 : KM];
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            const int cb = min(cb0 + j * NW, G.nbh - 1);
+            const uint8_t* zr = zs + (16 * cb + n) * S.rpitch;
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+              a[j][k] = *reinterpret_cast<const v4i*>(zr + aoff[k]);
+              if constexpr (ELEM != kU8) al[j][k] = *reinterpret_cast<const v4i*>(zr + S.zhalf + aoff[k]);
             }
-            if constexpr (split) acc = acc + acch * 128;
-            if (orow < G.row_end) {
-              const uint32_t y4 = b_quant4(acc, bv[lb * 16 + n]);
-              gdst_t op = G.dst + (int64_t)orow * S.out_pitch + col;
-              if (G.vec_out && col + 4 <= G.col_end) {
-                *(AOL_GLOBAL uint32_t*)op = y4;
-              } else {
+          }
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            const int cb = cb0 + j * NW;
+            if (j > 0 && cb >= G.nbh) break;
+            // uniform: the whole 16x16 output block inside the plane
+            const bool inside = rows_in && G.ocol0 + 16 * cb + 16 <= G.col_end;
+            const int col = G.ocol0 + 16 * cb + 4 * g;
+            if constexpr (ELEM == kU8) {
+              v4i acc = {bias, bias, bias, bias}, acch = {0, 0, 0, 0};
+#pragma unroll
+              for (int k = 0; k < KM; ++k) {
+                if (k > 0 && k >= nk) break;
+                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], bf[k], acc, 0, 0, 0);
+                if constexpr (split) acch = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], bfh[k], acch, 0, 0, 0);
+              }
+              if constexpr (split) acc = acc + acch * 128;
+              const uint32_t y4 = b_quant4(acc, 0);
+              if (inside) {
+                *(AOL_GLOBAL uint32_t*)(rowp + 16 * cb) = y4;
+              } else if (orow < G.row_end) {
+                gdst_t op = rowp + 16 * cb;
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                   if (col + i < G.col_end) op[i] = (uint8_t)(y4 >> (8 * i));
               }
-            }
-          } else {
-            v4f acc = {0.f, 0.f, 0.f, 0.f};
-            for (int kb = 0; kb < nk; ++kb) {
-              const int off = (((c0 + 4 * kb + g) * 8) & RM) * 2;
-              const v4i bf = fv[(fb + kb) * 64 + lane];
-              acc = b_mfma16<ELEM>(*reinterpret_cast<const v4i*>(zr + off), bf, acc);
-              acc = b_mfma16<ELEM>(*reinterpret_cast<const v4i*>(zr + S.zhalf + off), bf, acc);
-            }
-            if (orow < G.row_end) {
-              AOL_GLOBAL float* op = (AOL_GLOBAL float*)G.dst + (int64_t)orow * S.out_pitch + col;
-              if (G.vec_out && col + 4 <= G.col_end) {
-                *(AOL_GLOBAL v4f*)op = acc;
-              } else {
+            } else {
+              v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+              for (int k = 0; k < KM; ++k) {
+                if (k > 0 && k >= nk) break;
+                acc = b_mfma16<ELEM>(a[j][k], bf[k], acc);
+                acc = b_mfma16<ELEM>(al[j][k], bf[k], acc);
+              }
+              if (inside) {
+                *(AOL_GLOBAL v4f*)(rowp + 64 * cb) = acc;
+              } else if (orow < G.row_end) {
+                AOL_GLOBAL float* op = (AOL_GLOBAL float*)(rowp + 64 * cb);
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                   if (col + i < G.col_end) op[i] = acc[i];
@@ -511,38 +645,66 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
           }
         }
         ++B;
+        needB = __builtin_amdgcn_readlane(vneed, min(B, 63));
       }
-      lds_barrier();  // ring reads of this step done, step m+1 staged
+    };
+
+    lds_barrier();  // step 0 staged, coefficients in place
+    int zm = 0;     // ring line of step m's first intermediate line
+    for (int m = 0; m < G.M; ++m) {
+      // vertical blocks complete with step m-1's lines (the horizontal pass of
+      // step m writes other ring lines meanwhile)
+      vpass(min(G.Lz, 16 * m));
+      H.run(m, zm, g);  // this wave's share of step m's horizontal pass
+      zm = zm + 16 == S.ring ? 0 : zm + 16;
+      lds_barrier();  // step m's intermediate lines written, step m+1 staged
     }
+    vpass(G.Lz);    // the rest of the unit's vertical blocks
+    lds_barrier();  // the unit's LDS free
   }
 }
 
 using BandFn = void (*)(BandLaunch);
 
-template <int ELEM, bool SPLIT>
+template <int ELEM, bool SPLIT, int KM>
 static BandFn band_pick_s(int slots) {
-  if (slots <= 1) return k_band<ELEM, 1, SPLIT>;
-  if (slots <= 2) return k_band<ELEM, 2, SPLIT>;
-  if (slots <= 4) return k_band<ELEM, 4, SPLIT>;
-  return k_band<ELEM, 8, SPLIT>;
+  if (slots <= 1) return k_band<ELEM, 1, SPLIT, KM, false>;
+  if (slots <= 2) return k_band<ELEM, 2, SPLIT, KM, false>;
+  if (slots <= 4) return k_band<ELEM, 4, SPLIT, KM, false>;
+  return k_band<ELEM, 8, SPLIT, KM, false>;
 }
 
-static BandFn band_pick(int elem, int slots, bool split) {
-  if (elem == kU8) return split ? band_pick_s<kU8, true>(slots) : band_pick_s<kU8, false>(slots);
-  if (elem == kBF16) return band_pick_s<kBF16, false>(slots);
-  return band_pick_s<kFP16, false>(slots);
+// The gathering instance serves every slot and K-step count (the widest).
+template <int ELEM, bool SPLIT>
+static BandFn band_pick_k(int slots, int kmax, bool gather) {
+  if (gather) return k_band<ELEM, kBandMaxSlots, SPLIT, kMaxK, true>;
+  if (kmax <= 1) return band_pick_s<ELEM, SPLIT, 1>(slots);
+  return kmax <= 2 ? band_pick_s<ELEM, SPLIT, 2>(slots) : band_pick_s<ELEM, SPLIT, 4>(slots);
 }
 
-hipError_t band_prepare(int elem, int slots, bool split, size_t lds_bytes, int* wg_per_cu) {
-  const void* f = (const void*)band_pick(elem, slots, split);
-  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-  if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, f, kBandThreads, lds_bytes);
+static BandFn band_pick(int elem, int slots, bool split, int kmax, bool gather) {
+  if (elem == kU8) return split ? band_pick_k<kU8, true>(slots, kmax, gather) : band_pick_k<kU8, false>(slots, kmax, gather);
+  if (elem == kBF16) return band_pick_k<kBF16, false>(slots, kmax, gather);
+  return band_pick_k<kFP16, false>(slots, kmax, gather);
 }
 
-hipError_t band_launch(int elem, int slots, bool split, const BandLaunch& L, int grid, size_t lds_bytes,
-                       hipStream_t stream) {
-  hipLaunchKernelGGL(band_pick(elem, slots, split), dim3(grid), dim3(kBandThreads), lds_bytes, stream, L);
+hipError_t band_prepare(int elem, int slots, bool split, int kmax, size_t lds_bytes, int* wg_per_cu) {
+  // both instances (whole chunks, gathering) are launchable with this LDS
+  int wg[2] = {0, 0};
+  for (int gather = 0; gather < 2; ++gather) {
+    const void* f = (const void*)band_pick(elem, slots, split, kmax, gather != 0);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&wg[gather], f, kBandThreads, lds_bytes);
+    if (e != hipSuccess) return e;
+  }
+  *wg_per_cu = wg[0] < wg[1] ? wg[0] : wg[1];
+  return hipSuccess;
+}
+
+hipError_t band_launch(int elem, int slots, bool split, int kmax, bool gather, const BandLaunch& L, int grid,
+                       size_t lds_bytes, hipStream_t stream) {
+  hipLaunchKernelGGL(band_pick(elem, slots, split, kmax, gather), dim3(grid), dim3(kBandThreads), lds_bytes, stream, L);
   return hipGetLastError();
 }
 

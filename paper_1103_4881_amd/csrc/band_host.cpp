@@ -20,7 +20,9 @@ aol_status build_filter_bands(const FilterHost& hf, const FilterHost& vf, int el
   }
   const int E = elem == kU8 ? 16 : 8;
   // ring: run three periods of the schedule and keep the largest span between
-  // the oldest line a vertical block reads and the newest line written
+  // the oldest line a vertical block reads and the newest line written. A
+  // block whose window ends in step m's lines is computed during step m+1,
+  // while the horizontal pass writes that step's 16 lines.
   int span = 0, m = 0;
   for (int B = 0; B < 3 * vb.nblk; ++B) {
     const int per = B / vb.nblk, lb = B % vb.nblk;
@@ -28,13 +30,13 @@ aol_status build_filter_bands(const FilterHost& hf, const FilterHost& vf, int el
     while (16 * m < need) ++m;
     span = std::max(span, 16 * m - E * vb.chunk0[lb] - 16 * per * vb.q);
   }
-  int ring = 16;
-  while (ring < span + 16) ring *= 2;
+  const int ring = (span + 16 + 15) / 16 * 16;  // whole steps of 16 lines
   out.elem = elem;
   out.hb = hb;
   out.vb = vb;
   out.ring = ring;
   out.split = hb.split || vb.split;
+  out.kmax = std::max(hb.kmax, vb.kmax);
   if ((st = out.d_hb.upload(&hb, sizeof hb))) return st;
   if ((st = out.d_vb.upload(&vb, sizeof vb))) return st;
   if ((st = out.d_hfrag.upload(hfr.data(), hfr.size()))) return st;
@@ -54,7 +56,7 @@ static int layout(const FilterBands& fb, int nbh, int nch, BandStream& S) {
   S.lds_bh = S.lds_fv + fb.vb.nfrag * kLanes * 16;
   S.lds_bv = S.lds_bh + fb.hb.nblk * 16 * 4;
   S.lds_x = (S.lds_bv + fb.vb.nblk * 16 * 4 + 15) / 16 * 16;
-  S.lds_z = S.lds_x + 16 * S.xpitch;
+  S.lds_z = S.lds_x + 32 * S.xpitch;  // two staging buffers of 16 lines
   const int zbytes = nbh * 16 * S.rpitch;
   S.zhalf = fb.elem == kU8 ? 0 : zbytes;
   return S.lds_z + zbytes * (fb.elem == kU8 ? 1 : 2);
@@ -109,6 +111,8 @@ aol_status build_band_stream(const FilterBands& fb, int64_t h, int64_t w, int64_
   S.nch = nch;
   S.nch_magic = (uint32_t)((((uint64_t)1 << 32) + nch - 1) / nch);
   S.seg = seg > 0 ? (seg + 15) / 16 * 16 : 16 * std::max(1, (256 + 16 * vb.q - 1) / (16 * vb.q));
+  // at most 64 vertical output blocks per unit (one per lane of a table)
+  S.seg = std::min(S.seg, 16 * std::max(1, 64 / vb.p));
   S.vec_in = (w % E == 0) && (in_pitch % E == 0);
   S.vec_out = (out_pitch % 4 == 0) && ((hb.p * xr) % 4 == 0);
   S.hb = (const AxisBand*)fb.d_hb.ptr;

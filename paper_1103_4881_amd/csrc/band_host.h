@@ -14,7 +14,8 @@ namespace aol {
 struct FilterBands {
   int elem = kU8;
   AxisBand hb{}, vb{};
-  int ring = 0;       // intermediate lines the vertical pass needs kept (power of two)
+  int ring = 0;       // intermediate lines the vertical pass needs kept (a multiple of 16)
+  int kmax = 0;       // largest K-step count of a block of either axis
   bool split = false;
   DeviceBuf d_hb, d_vb, d_hfrag, d_vfrag;
 };
@@ -29,9 +30,10 @@ aol_status build_band_stream(const FilterBands& fb, int64_t h, int64_t w, int64_
 
 hipError_t set_pointers_launch(void** table, const void* const* ptrs, int n, hipStream_t stream);
 
-hipError_t band_prepare(int elem, int slots, bool split, size_t lds_bytes, int* wg_per_cu);
-hipError_t band_launch(int elem, int slots, bool split, const BandLaunch& L, int grid, size_t lds_bytes,
-                       hipStream_t stream);
+hipError_t band_prepare(int elem, int slots, bool split, int kmax, size_t lds_bytes, int* wg_per_cu);
+// gather: some line of the launch is not made of whole 16-byte chunks
+hipError_t band_launch(int elem, int slots, bool split, int kmax, bool gather, const BandLaunch& L, int grid,
+                       size_t lds_bytes, hipStream_t stream);
 
 aol_status build_band(const FilterHost& f, int tr, int elem, bool h_axis, bool force_split, AxisBand& band,
                       std::vector<uint8_t>& frags, const char* name);

@@ -40,6 +40,7 @@ struct aol_batch_plan {
   std::vector<int> filt;              // filter group of each stream
   std::vector<FilterBands> bands;     // one per filter group
   bool split = false;
+  int kmax = 0;  // largest K-step count over the filter groups
   Schedule sched;
   // built for the current schedule
   std::vector<BandStream> streams;
@@ -86,7 +87,7 @@ static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
   units.reserve(work.size());
   for (auto& w : work) units.push_back(w.second);
   int wg = 0;
-  hipError_t e = band_prepare(bp->elem, slots, bp->split, (size_t)lds, &wg);
+  hipError_t e = band_prepare(bp->elem, slots, bp->split, bp->kmax, (size_t)lds, &wg);
   if (e != hipSuccess) return hip_fail(e, "band kernel attributes");
   if (wg < 1) return fail(AOL_ERR_UNSUPPORTED, "batch schedule does not fit a compute unit");
   int dev = 0, cus = 0;
@@ -125,7 +126,9 @@ static aol_status batch_launch(aol_batch_plan* bp, hipStream_t stream) {
   L.total_units = (int32_t)bp->units.size();
   L.aligned = 1;  // checked by aol_batch_set_pointers
   L.ptr_table = (void* const*)bp->d_table.ptr;
-  hipError_t e = band_launch(bp->elem, bp->slots, bp->split, L, bp->grid, bp->lds, stream);
+  bool gather = false;
+  for (const BandStream& S : bp->streams) gather = gather || !S.vec_in;
+  hipError_t e = band_launch(bp->elem, bp->slots, bp->split, bp->kmax, gather, L, bp->grid, bp->lds, stream);
   if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
   return AOL_OK;
 }
@@ -259,6 +262,8 @@ aol_status aol_batch_plan_create(int32_t n_streams, const aol_stream_desc* strea
     bp->split = any_split;
     if (!any_split || pass == 1) break;
   }
+  bp->kmax = 0;
+  for (const FilterBands& fb : bp->bands) bp->kmax = std::max(bp->kmax, fb.kmax);
   bp->key = batch_key(bp);
   Schedule sc;
   if (tune_cache) {

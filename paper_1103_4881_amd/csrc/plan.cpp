@@ -229,7 +229,14 @@ aol_status build_band(const FilterHost& f, int tr, int elem, bool h_axis, bool f
     }
   }
   band.nchunks = chunk_hi;
+  // one all-zero fragment (pair) after the others: the operand of the K-steps
+  // a block does not need when every block runs the same number of them
+  band.zfrag = nfrag;
+  frags.resize(frags.size() + (size_t)(split ? 2 : 1) * kLanes * 16, 0);
+  nfrag += 1;
   band.nfrag = nfrag * (split ? 2 : 1);
+  band.kmax = 0;
+  for (int b = 0; b < band.nblk; ++b) band.kmax = std::max(band.kmax, band.nk[b]);
   return AOL_OK;
 }
 
@@ -389,7 +396,7 @@ static aol_status plan_build_band(aol_plan* pl, int xreps, int seg) {
       for (int xb = 0; xb < nxb; ++xb) units.push_back(BandUnit{i, xb, sy, 0});
   }
   int wg = 0;
-  hipError_t e = band_prepare(pl->elem, slots, fb.split, (size_t)lds, &wg);
+  hipError_t e = band_prepare(pl->elem, slots, fb.split, fb.kmax, (size_t)lds, &wg);
   if (e != hipSuccess) return hip_fail(e, "band kernel attributes");
   if (wg < 1) return AOL_OK;
   int dev = 0, cus = 0;
@@ -598,8 +605,11 @@ static aol_status run_fused(aol_plan* plan, int32_t n_frames, const void* const*
       if (n_frames > 1) aligned = aligned && in_fs[i] % ein == 0 && out_fs[i] % 4 == 0;
     }
     L.aligned = aligned ? 1 : 0;
+    bool gather = !aligned;
+    for (int i = 0; i < plan->n_planes; ++i) gather = gather || !plan->bstreams[i].vec_in;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(L.total_units, plan->bgrid));
-    hipError_t e = band_launch(plan->elem, plan->bslots, plan->fbands.split, L, grid, plan->blds, stream);
+    hipError_t e = band_launch(plan->elem, plan->bslots, plan->fbands.split, plan->fbands.kmax, gather, L, grid,
+                               plan->blds, stream);
     if (e != hipSuccess) return hip_fail(e, "band kernel launch");
     return ok();
   }
