@@ -37,7 +37,7 @@ struct alignas(16) AxisBand {
   int32_t nfrag;            // fragments (64 lanes x 16 B) of the whole band, the zero one included
   int32_t zfrag;            // K-step index of an all-zero fragment (after the others)
   int32_t kmax;             // largest nk of the band
-  int32_t pad2;
+  int32_t ubias;            // u8: every output has the same bias (all phases' taps have one sum)
   int32_t chunk0[kMaxNB];   // first chunk of block b's window
   int32_t nk[kMaxNB];       // K-steps (4 chunks each) of block b
   int32_t frag[kMaxNB];     // first fragment of block b (64 lanes x 16 B each)

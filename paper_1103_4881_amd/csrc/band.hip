@@ -181,7 +181,7 @@ template <int ELEM, int SLOTS>
 struct BandFeed {
   static constexpr int ES = ELEM == kU8 ? 1 : 2;
   static constexpr int E = 16 / ES;
-  gsrc_t base[SLOTS];  // the chunk's column in the plane's line 0
+  uint64_t p0[SLOTS];  // address of the chunk in step 0's line before the wrap (maybe outside the plane)
   int row[SLOTS];      // plane line of the chunk in step 0, before the wrap
   int xo[SLOTS];       // LDS byte offset of the chunk in the staging lines
 
@@ -199,7 +199,7 @@ struct BandFeed {
       row[s] = G.zrow0 + rr;
       int cl = G.a0 + c * E;
       if (cl < 0 || cl >= S.w) cl = bpmod(cl, S.w);
-      base[s] = G.src + (int64_t)cl * ES;
+      p0[s] = (uint64_t)(G.src + (int64_t)cl * ES) + (uint64_t)((int64_t)row[s] * S.in_pitch * ES);
     }
   }
 
@@ -214,20 +214,31 @@ struct BandFeed {
   // arithmetic, and a step past the unit loads its last line again. WRAP1:
   // the unit's lines lie within one plane height of the plane, so one
   // conditional add or subtract wraps them.
+  // Interior steps (uniform test: all 16 lines inside the plane and the
+  // unit's window) advance each chunk's address by 16 lines; the others
+  // clamp and wrap every line. Both paths load the same registers in the
+  // same order.
   template <bool WRAP1>
   __device__ __forceinline__ void issue(v4i (&pre)[SLOTS], const BandStream& S, const BandUnitGeo& G, int m) const {
-    const int last = G.zrow0 + G.Lz - 1;
-    const uint32_t pitch = (uint32_t)(S.in_pitch * ES);
+    const int top = G.zrow0 + 16 * m;
+    const int64_t pitch = S.in_pitch * ES;
+    if (top >= 0 && top + 16 <= S.h && 16 * m + 16 <= G.Lz) {
+      const uint64_t adv = (uint64_t)(16 * m) * (uint64_t)pitch;
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-      int gr = min(row[s] + 16 * m, last);
-      if constexpr (WRAP1) {
-        gr = gr < 0 ? gr + S.h : gr;
-        gr = gr >= S.h ? gr - S.h : gr;
-      } else {
-        gr = bpmod(gr, S.h);
+      for (int s = 0; s < SLOTS; ++s) pre[s] = *(const AOL_GLOBAL v4i*)(p0[s] + adv);
+    } else {
+      const int last = G.zrow0 + G.Lz - 1;
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) {
+        int gr = min(row[s] + 16 * m, last);
+        if constexpr (WRAP1) {
+          gr = gr < 0 ? gr + S.h : gr;
+          gr = gr >= S.h ? gr - S.h : gr;
+        } else {
+          gr = bpmod(gr, S.h);
+        }
+        pre[s] = *(const AOL_GLOBAL v4i*)(p0[s] + (uint64_t)((int64_t)(gr - row[s]) * pitch));
       }
-      pre[s] = *(const AOL_GLOBAL v4i*)(base[s] + (uint64_t)(uint32_t)gr * pitch);
     }
   }
 
@@ -237,7 +248,7 @@ struct BandFeed {
   __device__ __forceinline__ void stage_gathered(const BandStream& S, const BandUnitGeo& G, int m, uint8_t* xs) const {
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-      const int col = (int)((base[s] - G.src) / ES);
+      const int col = (int)(((int64_t)(p0[s] - (uint64_t)G.src) - (int64_t)row[s] * S.in_pitch * ES) / ES);
       const v4i a = b_load_chunk_wrap<ES>(line(S, G, m, s), col, S.w);
       *reinterpret_cast<v4i*>(xs + xo[s]) = ELEM == kU8 ? b_to_i8(a) : a;
     }
@@ -251,95 +262,107 @@ struct BandFeed {
   }
 };
 
-// Horizontal-pass block table of one wave for one unit: lane i describes
-// the wave's i-th block (w + 16*i), read back with readlane.
-// Bits 0-15: byte offset of the block's first chunk in a staged line;
-// 16-23: first coefficient fragment; 24-28: block within the period; 29-31:
-// K-steps.
-__device__ __forceinline__ uint32_t hblock_entry(cband_t hb, int b, int E) {
-  const int per = b / hb->nblk, lb = b - per * hb->nblk;
-  const int c0 = hb->chunk0[lb] + per * (hb->q * 16 / E);  // a period is 16q elements
-  return (uint32_t)(c0 * 16) | ((uint32_t)hb->frag[lb] << 16) | ((uint32_t)lb << 24) | ((uint32_t)hb->nk[lb] << 29);
-}
-
-// One horizontal block's operands: KM K-steps of A (16 staged lines x 4
-// chunks) and B (coefficients); steps past the block's own nk read its first
-// chunk against the zero fragment.
-template <int ELEM, bool SPLIT, int KM>
-struct HOps {
-  v4i a[KM], b[KM], bh[SPLIT ? KM : 1];
-  int bias, nk;
-  __device__ __forceinline__ void load(uint32_t t, const uint8_t* xl, const uint8_t* fl, const uint8_t* bl, int zfrag) {
-    const int c0 = (int)(t & 0xFFFFu), fb = (int)((t >> 16) & 0xFFu), lb = (int)((t >> 24) & 31u);
-    nk = (int)(t >> 29);
-#pragma unroll
-    for (int k = 0; k < KM; ++k) {
-      const bool on = k < nk;
-      a[k] = *reinterpret_cast<const v4i*>(xl + (on ? c0 + 64 * k : c0));
-      const int f = on ? fb + k : zfrag;
-      if constexpr (SPLIT) {
-        b[k] = *reinterpret_cast<const v4i*>(fl + (2 * f) * 1024);
-        bh[k] = *reinterpret_cast<const v4i*>(fl + (2 * f + 1) * 1024);
-      } else {
-        b[k] = *reinterpret_cast<const v4i*>(fl + f * 1024);
-      }
-    }
-    if constexpr (ELEM == kU8) bias = *reinterpret_cast<const int*>(bl + lb * 64);
-  }
-};
-
-// Horizontal pass of one step by one wave (every wave of the workgroup
-// takes part: blocks w, w + 16, ...): 16 intermediate lines of each of its
-// 16-column blocks, written transposed into the ring.
+// Horizontal pass of one step by one wave. Every wave of the workgroup
+// takes part, and each takes blocks of one position lb within the period
+// (waves w = lb, lb + nblk, ...: wave w handles blocks lb + nblk*(w/nblk +
+// gw*i), gw the waves sharing lb), so its coefficient operands and biases
+// are the same for all its blocks and stay in registers for the whole unit,
+// and its blocks' staged chunks and ring rows advance by fixed strides.
+// Writes 16 intermediate lines of each of its 16-column blocks, transposed,
+// into the ring.
 template <int ELEM, bool SPLIT, int KM, int NB>  // NB: blocks per iteration (operands in flight)
 struct BandH {
   static constexpr int ES = ELEM == kU8 ? 1 : 2;
   static constexpr int E = 16 / ES;
-  uint32_t tbl;
-  int nbi, hz, xbuf, zstep, zhalf;
-  const uint8_t* xl;   // lane's staged line and chunk of a K-step (buffer 0)
-  const uint8_t* fhl;  // lane's slot of a coefficient fragment
-  const uint8_t* bhl;  // lane's bias of block 0 of a period
-  uint8_t* zl;         // lane's ring row of the wave's first block
+  // operands of four K-steps would not fit in registers beside the vertical
+  // pass's: read from LDS for every block instead
+  static constexpr bool CACHE = KM <= 2;
+  v4i bf[CACHE ? KM : 1], bfh[SPLIT && CACHE ? KM : 1];  // coefficient operands of the wave's position
+  const uint8_t* fl;  // lane's slot of the position's first fragment
+  const uint8_t* bl;  // lane's bias
+  v4i bq;                           // integer form: the rounding bias, every output of the lane's column
+  int nbi, nk, astep, zstep, xbuf, zhalf;
+  const uint8_t* xa;  // lane's A chunk of the wave's first block (staging buffer 0)
+  uint8_t* zl;        // lane's ring row of the wave's first block
 
   __device__ __forceinline__ void setup(const BandStream& S, const BandUnitGeo& G, const uint8_t* lds, int w,
                                         int lane) {
     const cband_t hb = (cband_t)S.hb;
     const int g = lane >> 4, n = lane & 15;
-    nbi = w < G.nbh ? (G.nbh - w + kBandWaves - 1) / kBandWaves : 0;
-    tbl = lane < nbi ? hblock_entry(hb, w + kBandWaves * lane, E) : 0u;
-    hz = hb->zfrag;
+    const int nblk = hb->nblk;
+    const int lb = w % nblk, r = w / nblk;
+    const int gw = (kBandWaves - lb + nblk - 1) / nblk;  // waves with this position
+    const int b0 = lb + nblk * r, bstep = nblk * gw;
+    nbi = b0 < G.nbh ? (G.nbh - b0 + bstep - 1) / bstep : 0;
+    nk = hb->nk[lb];
+    const int fb = hb->frag[lb];
+    fl = lds + S.lds_fh + lane * 16 + fb * (SPLIT ? 2048 : 1024);
+    bl = lds + S.lds_bh + (lb * 16 + n) * 4;
+    const int per0 = b0 / nblk;          // period of the first block
+    const int pchunks = hb->q * 16 / E;  // chunks per period (16q elements)
+    xa = lds + S.lds_x + n * S.xpitch + (hb->chunk0[lb] + per0 * pchunks + g) * 16;
+    astep = gw * pchunks * 16;
+    zl = const_cast<uint8_t*>(lds) + S.lds_z + (16 * b0 + n) * S.rpitch;
+    zstep = 16 * bstep * S.rpitch;
     xbuf = 16 * S.xpitch;
-    zstep = 16 * kBandWaves * S.rpitch;
     zhalf = S.zhalf;
-    xl = lds + S.lds_x + n * S.xpitch + g * 16;
-    fhl = lds + S.lds_fh + lane * 16;
-    bhl = lds + S.lds_bh + n * 4;
-    zl = const_cast<uint8_t*>(lds) + S.lds_z + (16 * w + n) * S.rpitch;
+  }
+
+  // the position's operands, once the unit's coefficients are in LDS (after
+  // the unit's first barrier)
+  __device__ __forceinline__ void load_operands() {
+    if constexpr (CACHE) {
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (k < nk || k == 0) {  // uniform; unused K-steps are never multiplied
+          if constexpr (SPLIT) {
+            bf[k] = *reinterpret_cast<const v4i*>(fl + (2 * k) * 1024);
+            bfh[k] = *reinterpret_cast<const v4i*>(fl + (2 * k + 1) * 1024);
+          } else {
+            bf[k] = *reinterpret_cast<const v4i*>(fl + k * 1024);
+          }
+        }
+      }
+    }
+    if constexpr (ELEM == kU8) {
+      const int bias = *reinterpret_cast<const int*>(bl);
+      bq = v4i{bias, bias, bias, bias};
+    }
   }
 
   // zm: ring line of step m's first intermediate line
   __device__ __forceinline__ void run(int m, int zm, int g) const {
-    const uint8_t* xm = xl + (m & 1) * xbuf;
+    const uint8_t* xm = xa + (m & 1) * xbuf;
     uint8_t* zrow = zl + (zm + 4 * g) * ES;  // lane's 4 intermediate lines in its ring row
     for (int i = 0; i < nbi; i += NB) {
-      HOps<ELEM, SPLIT, KM> op[NB];
+      v4i a[NB][KM];
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         const int ii = min(i + j, nbi - 1);  // a missing block repeats the last one
-        op[j].load(__builtin_amdgcn_readlane(tbl, ii), xm, fhl, bhl, hz);
+#pragma unroll
+        for (int k = 0; k < KM; ++k)
+          if (k == 0 || k < nk) a[j][k] = *reinterpret_cast<const v4i*>(xm + ii * astep + 64 * k);
       }
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         if (j > 0 && i + j >= nbi) break;
         uint8_t* zp = zrow + (i + j) * zstep;
         if constexpr (ELEM == kU8) {
-          v4i acc = {op[j].bias, op[j].bias, op[j].bias, op[j].bias}, acch = {0, 0, 0, 0};
+          v4i acc = bq, acch = {0, 0, 0, 0};
 #pragma unroll
           for (int k = 0; k < KM; ++k) {
-            if (k > 0 && k >= op[j].nk) break;  // uniform: the block's own K-steps only
-            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(op[j].a[k], op[j].b[k], acc, 0, 0, 0);
-            if constexpr (SPLIT) acch = __builtin_amdgcn_mfma_i32_16x16x64_i8(op[j].a[k], op[j].bh[k], acch, 0, 0, 0);
+            if (k > 0 && k >= nk) break;  // uniform: the position's own K-steps only
+            if constexpr (CACHE) {
+              acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], bf[k], acc, 0, 0, 0);
+              if constexpr (SPLIT) acch = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], bfh[k], acch, 0, 0, 0);
+            } else if constexpr (SPLIT) {
+              const v4i lo = *reinterpret_cast<const v4i*>(fl + (2 * k) * 1024);
+              const v4i hi = *reinterpret_cast<const v4i*>(fl + (2 * k + 1) * 1024);
+              acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], lo, acc, 0, 0, 0);
+              acch = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], hi, acch, 0, 0, 0);
+            } else {
+              acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], *reinterpret_cast<const v4i*>(fl + k * 1024), acc, 0, 0, 0);
+            }
           }
           if constexpr (SPLIT) acc = acc + acch * 128;
           // kept as signed bytes z - 128, the vertical pass's operand
@@ -348,8 +371,9 @@ struct BandH {
           v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int k = 0; k < KM; ++k) {
-            if (k > 0 && k >= op[j].nk) break;
-            acc = b_mfma16<ELEM>(op[j].a[k], op[j].b[k], acc);
+            if (k > 0 && k >= nk) break;
+            if constexpr (CACHE) acc = b_mfma16<ELEM>(a[j][k], bf[k], acc);
+            else acc = b_mfma16<ELEM>(a[j][k], *reinterpret_cast<const v4i*>(fl + k * 1024), acc);
           }
           // hi/lo pair: hi = round(z), lo = round(z - hi)
           const uint32_t h01 = b_pack2<ELEM>(acc[0], acc[1]);
@@ -373,7 +397,7 @@ struct BandH {
 // them).
 template <int ELEM, int SLOTS, bool WRAP1, class HP>
 __device__ __forceinline__ void band_feed_unit(const BandFeed<ELEM, SLOTS>& F, const BandStream& S,
-                                               const BandUnitGeo& G, uint8_t* xs, const HP& H, int g) {
+                                               const BandUnitGeo& G, uint8_t* xs, HP& H, int g) {
   constexpr int D = BandDepth<SLOTS>::value;
   const int xbuf = 16 * S.xpitch;  // bytes from staging buffer 0 to buffer 1
   v4i pre[D][SLOTS];
@@ -381,7 +405,8 @@ __device__ __forceinline__ void band_feed_unit(const BandFeed<ELEM, SLOTS>& F, c
   for (int k = 0; k < D; ++k) F.template issue<WRAP1>(pre[k], S, G, k);
   F.commit(pre[0], xs);
   F.template issue<WRAP1>(pre[0], S, G, D);
-  lds_barrier();  // step 0 staged
+  lds_barrier();  // step 0 staged, the unit's coefficients in place
+  H.load_operands();
   // Every iteration commits and re-issues one register set, so the loads in
   // flight at the loop head are the same sets in the same order on entry and
   // on the back edge. Steps past the unit stage its last line again into a
@@ -418,10 +443,11 @@ __device__ __forceinline__ void band_feed_unit(const BandFeed<ELEM, SLOTS>& F, c
 // The same for lines that are gathered element by element: no prefetch.
 template <int ELEM, int SLOTS, class HP>
 __device__ __forceinline__ void band_feed_unit_gathered(const BandFeed<ELEM, SLOTS>& F, const BandStream& S,
-                                                        const BandUnitGeo& G, uint8_t* xs, const HP& H, int g) {
+                                                        const BandUnitGeo& G, uint8_t* xs, HP& H, int g) {
   const int xbuf = 16 * S.xpitch;
   F.stage_gathered(S, G, 0, xs);
-  lds_barrier();  // step 0 staged
+  lds_barrier();  // step 0 staged, the unit's coefficients in place
+  H.load_operands();
   int zm = 0;
   for (int m = 0; m < G.M; ++m) {
     if (m + 1 < G.M) F.stage_gathered(S, G, m + 1, xs + ((m + 1) & 1) * xbuf);
@@ -489,7 +515,7 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
   constexpr int E = 16 / ES;
   constexpr bool split = (ELEM == kU8) && SPLIT;
   constexpr int NW = (kBandThreads - kBandLoadThreads) / 64;  // compute waves
-  constexpr int NB = KM <= 2 && !split ? 4 : 2;               // blocks per iteration (operands in flight)
+  constexpr int NB = KM <= 2 && !split ? 4 : 1;               // blocks per iteration (operands in flight)
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -524,7 +550,6 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
     band_unit<ELEM>(L, u, S, G);
     const cband_t hb = (cband_t)S.hb;
     const cband_t vb = (cband_t)S.vb;
-    uint8_t* xs = lds + S.lds_x;
     uint8_t* zs = lds + S.lds_z;
     const uint8_t* fh = lds + S.lds_fh;
     const uint8_t* fv = lds + S.lds_fv;
@@ -650,6 +675,7 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
     };
 
     lds_barrier();  // step 0 staged, coefficients in place
+    H.load_operands();
     int zm = 0;     // ring line of step m's first intermediate line
     for (int m = 0; m < G.M; ++m) {
       // vertical blocks complete with step m-1's lines (the horizontal pass of

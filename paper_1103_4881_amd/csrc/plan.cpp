@@ -237,6 +237,8 @@ aol_status build_band(const FilterHost& f, int tr, int elem, bool h_axis, bool f
   band.nfrag = nfrag * (split ? 2 : 1);
   band.kmax = 0;
   for (int b = 0; b < band.nblk; ++b) band.kmax = std::max(band.kmax, band.nk[b]);
+  band.ubias = 1;
+  for (int i = 0; i < band.nblk * 16; ++i) band.ubias = band.ubias && band.bias[i] == band.bias[0];
   return AOL_OK;
 }
 

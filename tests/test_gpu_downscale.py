@@ -23,6 +23,10 @@ FLOAT_TOL = 1e-3
 def _filters(p, q, T, kind="design", seed=0, starts=None):
     if kind == "design":
         c = synthgen.design_taps(p, q, T)
+    elif kind == "raw":
+        # phases whose taps have different sums: a different rounding bias per output phase
+        g = synthgen.rng_for(seed, 6)
+        c = g.integers(-60, 120, size=(p, T))
     else:
         g = synthgen.rng_for(seed, 5)
         c = g.integers(-300, 400, size=(p, T))
@@ -83,6 +87,8 @@ CASES = [
     (240, 200, 16, 64, 32, "random", None),
     (77, 333, 3, 5, 13, "random", [-9, -4, 0]),
     (540, 960, 3, 8, 11, "design", None),
+    (96, 256, 3, 8, 11, "raw", None),
+    (70, 150, 2, 3, 9, "raw", None),
 ]
 
 
