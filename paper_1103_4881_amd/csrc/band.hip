@@ -582,7 +582,13 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
     H.setup(S, G, lds, wave, lane);
     uint32_t vtbl = 0;
     int vneed = 0;
-    if (lane < G.NBV) vblock_entry(vb, lane, E, S.ring, G.Lz, vtbl, vneed);
+    for (int b = 0; b < G.NBV; ++b) {  // scalar reads of the descriptor, one lane written per block
+      uint32_t ent;
+      int need;
+      vblock_entry(vb, b, E, S.ring, G.Lz, ent, need);
+      vtbl = lane == b ? ent : vtbl;
+      vneed = lane == b ? need : vneed;
+    }
     const int vz = vb->zfrag;
     const uint8_t* fvl = fv + lane * 16;
     int B = 0;  // next vertical block
