@@ -259,24 +259,27 @@ def bench_generic(steps=10, warmup=2):
     y = torch.empty(plan.out_shape, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
     ms_step, ms_kernel, _ = time_launches(lambda: plan.run(x, y), steps, warmup, stream)
-    # footprint: every input element some pattern element reads (bitmap on the device)
+    # footprint: every input element some pattern element reads (bitmap on the device,
+    # a few large batched index computations)
     R = rt.rep_shape
     seen = torch.zeros(int(np.prod(GEN_SHAPE)), dtype=torch.bool, device="cuda")
-    S = torch.tensor(GEN_SHAPE, device="cuda")
-    strides = torch.tensor([GEN_SHAPE[1] * GEN_SHAPE[2], GEN_SHAPE[2], 1], device="cuda")
+    S = torch.tensor(GEN_SHAPE, device="cuda").view(3, 1, 1, 1, 1)
+    strides = [GEN_SHAPE[1] * GEN_SHAPE[2], GEN_SHAPE[2], 1]
     P = torch.tensor(rt.paving, device="cuda")
     F = torch.tensor(rt.fitting, device="cuda")
     o = torch.tensor(rt.origin, device="cuda")
-    for r0 in range(R[0]):
-        r1 = torch.arange(R[1], device="cuda").view(-1, 1)
-        r2 = torch.arange(R[2], device="cuda").view(1, -1)
-        for i0 in range(5):
-            for i1 in range(5):
-                flat = 0
-                for d in range(3):
-                    v = o[d] + P[d, 0] * r0 + P[d, 1] * r1 + P[d, 2] * r2 + F[d, 0] * i0 + F[d, 1] * i1
-                    flat = flat + torch.remainder(v, S[d]) * strides[d]
-                seen[flat.reshape(-1)] = True
+    pat = torch.stack(torch.meshgrid(torch.arange(5, device="cuda"), torch.arange(5, device="cuda"),
+                                     indexing="ij")).reshape(2, -1)  # [2, 25]
+    foff = (F.view(3, 2, 1) * pat.view(1, 2, 25)).sum(1).view(3, 1, 1, 1, 25)
+    r1 = torch.arange(R[1], device="cuda").view(1, 1, -1, 1, 1)
+    r2 = torch.arange(R[2], device="cuda").view(1, 1, 1, -1, 1)
+    for c0 in range(0, R[0], 32):
+        r0 = torch.arange(c0, min(c0 + 32, R[0]), device="cuda").view(1, -1, 1, 1, 1)
+        v = (o.view(3, 1, 1, 1, 1) + P[:, 0].view(3, 1, 1, 1, 1) * r0 + P[:, 1].view(3, 1, 1, 1, 1) * r1
+             + P[:, 2].view(3, 1, 1, 1, 1) * r2 + foff)
+        v = torch.remainder(v, S)
+        flat = v[0] * strides[0] + v[1] * strides[1] + v[2]
+        seen[flat.reshape(-1)] = True
     footprint = int(seen.sum().item())
     n_out = int(np.prod(R))
     alg_bytes = 4 * footprint + 4 * n_out

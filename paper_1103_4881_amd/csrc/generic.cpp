@@ -12,6 +12,7 @@
 
 namespace aol {
 hipError_t wsum_launch(const WsumArgs& a, int64_t blocks, hipStream_t stream);
+hipError_t wsum_prepare();
 }
 
 using namespace aol;
@@ -224,6 +225,84 @@ aol_status aol_wsum_plan_create(const aol_tiler* in, const aol_tiler* out, const
   if (blocks >= (1LL << 31)) {
     delete p;
     return fail(AOL_ERR_UNSUPPORTED, "repetition space needs too many workgroups");
+  }
+
+  // Staged form: the box of input elements one 64x64 block of points reads,
+  // when it is small enough for LDS and no pattern spans an array extent.
+  {
+    bool fit = true;
+    int64_t fmin[kWsumMaxRank] = {0, 0, 0, 0}, fmax[kWsumMaxRank] = {0, 0, 0, 0};
+    for (int d = 0; d < a.ra; ++d) {
+      fit = fit && a.hi[d] < a.S[d] && -a.lo[d] < a.S[d];
+      fmin[d] = a.lo[d];
+      fmax[d] = a.hi[d];
+      for (int k = 0; k < a.rr; ++k) {
+        const int32_t v = a.P[d][k];  // in [0, S)
+        a.Ps[d][k] = (int64_t)v * 2 > a.S[d] ? v - a.S[d] : v;
+      }
+    }
+    int64_t elems = 1;
+    for (int d = 0; d < a.ra && fit; ++d) {
+      int64_t ext = fmax[d] - fmin[d] + 1, lo = fmin[d];
+      for (int k : {k_lane, k_loop}) {
+        const int64_t span = (int64_t)a.Ps[d][k] * (k == k_lane ? 63 : 4 * kWsumBoxPoints - 1);
+        ext += span < 0 ? -span : span;
+        lo += span < 0 ? span : 0;
+      }
+      fit = fit && ext <= 2 * (int64_t)a.S[d];  // a box longer than the array holds some elements twice
+      a.bn[d] = (int32_t)ext;
+      a.dlo[d] = (int32_t)lo;
+      elems *= ext;
+    }
+    fit = fit && elems * 4 <= kWsumBoxMaxBytes && p->in_elems * 4 < (1LL << 32);
+    if (fit) {
+      int64_t bst[kWsumMaxRank] = {0, 0, 0, 0}, s1 = 1;
+      for (int d = a.ra - 1; d >= 0; --d) {
+        bst[d] = s1;
+        s1 *= a.bn[d];
+      }
+      a.box_elems = (int32_t)elems;
+      a.box_rows = (int32_t)(elems / a.bn[a.ra - 1]);
+      int64_t ls = 0, js = 0;
+      for (int d = 0; d < a.ra; ++d) {
+        ls += (int64_t)a.Ps[d][k_lane] * bst[d];
+        js += (int64_t)a.Ps[d][k_loop] * bst[d];
+      }
+      a.lstep = (int32_t)ls;
+      a.jstep = (int32_t)js;
+      for (int i = 0; i < npat; ++i) {
+        int64_t idx[AOL_MAX_RANK] = {0, 0, 0, 0};
+        int rem = i;
+        for (int b = in->pat_rank - 1; b >= 0; --b) {
+          idx[b] = rem % in->pat_shape[b];
+          rem /= (int)in->pat_shape[b];
+        }
+        int64_t o = 0;
+        for (int d = 0; d < a.ra; ++d) {
+          int64_t f = 0;
+          for (int b = 0; b < in->pat_rank; ++b) f += in->fitting[d][b] * idx[b];
+          o += (f - a.dlo[d]) * bst[d];
+        }
+        a.offl[i] = (int32_t)o;
+      }
+    }
+    a.use_box = fit ? 1 : 0;
+    if (fit) {  // blocks of 64 x 4*kWsumBoxPoints points
+      const int64_t nb = (R[k_loop] + 4 * kWsumBoxPoints - 1) / (4 * kWsumBoxPoints);
+      blocks = blocks / a.nb_loop * nb;
+      a.nb_loop = (int32_t)nb;
+      if (blocks >= (1LL << 31)) {
+        delete p;
+        return fail(AOL_ERR_UNSUPPORTED, "repetition space needs too many workgroups");
+      }
+    }
+    if (fit) {
+      hipError_t e = wsum_prepare();
+      if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "weighted-sum kernel attributes");
+      }
+    }
   }
   p->blocks = blocks;
   *plan = p;

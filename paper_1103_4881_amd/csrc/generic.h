@@ -32,6 +32,21 @@ struct WsumArgs {
   int32_t other[kWsumMaxRank];
   int32_t n_other;
   int32_t transpose;                     // stage results in LDS and store along k_loop
+  // Staged form: the input box a 64x64 block of points reads (unwrapped
+  // coordinates lo + [0, bn) per dim, lo = o + Ps.r_corner + dlo) is loaded
+  // into LDS once; pattern element i of point (lane, jj) is then
+  // box[lane*lstep + jj*jstep + offl[i]].
+  int32_t use_box;
+  int32_t Ps[kWsumMaxRank][kWsumMaxRank];  // paving, signed representative nearest zero
+  int32_t dlo[kWsumMaxRank];             // box origin relative to the block's corner point
+  int32_t bn[kWsumMaxRank];              // box extent per dim
+  int32_t box_rows;                      // product of the extents of all but the last dim
+  int32_t box_elems;
+  int32_t lstep, jstep;                  // box offset per lane / per loop point
+  int32_t offl[kMaxPat];                 // box offset of each pattern element (dlo folded in)
 };
+
+constexpr int kWsumBoxMaxBytes = 48 * 1024;  // box in LDS per workgroup
+constexpr int kWsumBoxPoints = 8;            // staged form: points per thread along the loop dimension
 
 }  // namespace aol
