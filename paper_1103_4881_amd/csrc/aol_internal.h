@@ -108,25 +108,43 @@ struct BandStream {
   int32_t ring;            // intermediate lines kept (a multiple of 16)
   int32_t rpitch;          // bytes between rows of the ring (of each half for the float form)
   int32_t zhalf;           // float form: bytes from the hi ring to the lo ring
-  int32_t xpitch;          // bytes between staged lines (two buffers of 16 lines)
-  int32_t lds_x, lds_z, lds_fh, lds_fv, lds_bh, lds_bv;  // LDS byte offsets
+  int32_t xpitch;          // bytes between staged lines
+  // LDS byte offsets. The two staging buffers of 16 lines sit at the same
+  // place for every stream of a launch (buffer 1 at lds_x + xbuf, xbuf from
+  // the widest stream), apart from every stream's coefficients and ring, so
+  // the next unit's first lines can be staged while a unit finishes.
+  int32_t lds_x, lds_z, lds_fh, lds_fv, lds_bh, lds_bv;
   int32_t vec_in;          // line length a multiple of one chunk and pitch chunk aligned
   int32_t vec_out;         // output pitch a multiple of 4 elements
-  int32_t pad0, pad1;
+  int32_t xbuf;            // bytes from staging buffer 0 to buffer 1 (the same for every stream of a launch)
+  int32_t lds_vt;          // LDS byte offset of the vertical block table (64 entries, then 64 window ends)
   const AxisBand* hb;      // one period (16 repetitions) of each axis
   const AxisBand* vb;
   const void* hfrag;
   const void* vfrag;
+  const void* vtab;        // vertical block table (copied into LDS at lds_vt)
 };
 
-// One unit of work of one frame: stream, column band, segment.
+// One unit of work of one frame (a column band of a stream and a segment
+// of repetitions down it) with its geometry, computed on the host.
 struct BandUnit {
-  int32_t stream, xb, sy, pad;
+  int32_t stream, ptr;     // stream, its entry in the pointer table
+  int32_t zrow0, Lz;       // input lines [zrow0, zrow0 + Lz) the unit reads (before the wrap)
+  int32_t M, NBV;          // steps of 16 lines, vertical output blocks
+  int32_t a0;              // first input column of the staged band lines (before the wrap)
+  int32_t orow0, ocol0;    // first output row and column
+  int32_t row_end, col_end;  // output rows and columns end (exclusive, inside the plane)
+  int32_t nbh;             // 16-column output blocks
+  int32_t pad[4];
 };
 
 struct BandLaunch {
   const BandStream* streams;
   const BandUnit* units;         // the units of one frame
+  // Unit ids (frame * units_per_frame + unit) grouped by workgroup:
+  // workgroup g takes order[first[g]], ..., order[first[g + 1] - 1], in turn.
+  const int32_t* order;
+  const int32_t* first;
   int32_t units_per_frame, n_frames, total_units;
   int32_t aligned;               // every pointer 16-byte aligned (inputs) / 16-byte (outputs)
   void* const* ptr_table;        // device [in, out] pointer per stream, or NULL: use ptrs below

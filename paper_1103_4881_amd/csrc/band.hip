@@ -185,17 +185,31 @@ struct BandFeed {
   int row[SLOTS];      // plane line of the chunk in step 0, before the wrap
   int xo[SLOTS];       // LDS byte offset of the chunk in the staging lines
 
-  __device__ __forceinline__ void setup(const BandStream& S, const BandUnitGeo& G, int ltid) {
+  // lane's chunks: line rr and chunk c of the band line. A lane past the
+  // last chunk loads and stores chunk 0 of line 15 again: the same bytes to
+  // the same place, and no branch around the store, which would leave its
+  // register's load outstanding on the other path.
+  static __device__ __forceinline__ void chunk_of(const BandStream& S, int idx, int& rr, int& c) {
+    rr = (int)__umulhi((uint32_t)idx, S.nch_magic);  // idx / nch
+    c = idx - rr * S.nch;
+    if (rr >= 16) { rr = 15; c = 0; }
+  }
+
+  // staging offsets of the lane's chunks (depend on the stream only)
+  static __device__ __forceinline__ void offsets(const BandStream& S, int ltid, int (&xo)[SLOTS]) {
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-      const int idx = ltid + s * kBandLoadThreads;
-      int rr = (int)__umulhi((uint32_t)idx, S.nch_magic);  // idx / nch
-      int c = idx - rr * S.nch;
-      // a lane past the last chunk loads and stores chunk 0 of line 15 again:
-      // the same bytes to the same place, and no branch around the store,
-      // which would leave its register's load outstanding on the other path
-      if (rr >= 16) { rr = 15; c = 0; }
+      int rr, c;
+      chunk_of(S, ltid + s * kBandLoadThreads, rr, c);
       xo[s] = rr * S.xpitch + c * 16;
+    }
+  }
+
+  __device__ __forceinline__ void addresses(const BandStream& S, const BandUnitGeo& G, int ltid) {
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      int rr, c;
+      chunk_of(S, ltid + s * kBandLoadThreads, rr, c);
       row[s] = G.zrow0 + rr;
       int cl = G.a0 + c * E;
       if (cl < 0 || cl >= S.w) cl = bpmod(cl, S.w);
@@ -203,40 +217,38 @@ struct BandFeed {
     }
   }
 
+  __device__ __forceinline__ void setup(const BandStream& S, const BandUnitGeo& G, int ltid) {
+    addresses(S, G, ltid);
+    offsets(S, ltid, xo);
+  }
+
   __device__ __forceinline__ gsrc_t line(const BandStream& S, const BandUnitGeo& G, int m, int s) const {
     const int grow = bpmod(min(row[s] + 16 * m, G.zrow0 + G.Lz - 1), S.h);
     return G.src + (int64_t)grow * S.in_pitch * ES;
   }
 
-  // Whole chunks of a circular line (a wrapped chunk is another chunk).
-  // Straight-line code with the same loads on every path, so the compiler's
-  // count of loads in flight stays exact: rows are clamped and wrapped with
-  // arithmetic, and a step past the unit loads its last line again. WRAP1:
-  // the unit's lines lie within one plane height of the plane, so one
-  // conditional add or subtract wraps them.
-  // Interior steps (uniform test: all 16 lines inside the plane and the
-  // unit's window) advance each chunk's address by 16 lines; the others
-  // clamp and wrap every line. Both paths load the same registers in the
-  // same order.
-  template <bool WRAP1>
-  __device__ __forceinline__ void issue(v4i (&pre)[SLOTS], const BandStream& S, const BandUnitGeo& G, int m) const {
-    const int top = G.zrow0 + 16 * m;
-    const int64_t pitch = S.in_pitch * ES;
-    if (top >= 0 && top + 16 <= S.h && 16 * m + 16 <= G.Lz) {
+  // Whole chunks of a circular line (a wrapped chunk is another chunk) of
+  // step m of a unit with h plane lines, `pitch` bytes apart, and window
+  // [zrow0, zrow0 + Lz). Straight-line code with the same loads on every
+  // path, so the compiler's count of loads in flight stays exact: rows are
+  // clamped and wrapped with arithmetic, and a step past the unit loads its
+  // last line again. Interior steps (uniform test: all 16 lines inside the
+  // plane and the window) advance each chunk's address by 16 lines; the
+  // others clamp and wrap every line. Both paths load the same registers in
+  // the same order.
+  __device__ __forceinline__ void issue(v4i (&pre)[SLOTS], int h, int64_t pitch, int zrow0, int Lz, int m) const {
+    const int top = zrow0 + 16 * m;
+    if (top >= 0 && top + 16 <= h && 16 * m + 16 <= Lz) {
       const uint64_t adv = (uint64_t)(16 * m) * (uint64_t)pitch;
 #pragma unroll
       for (int s = 0; s < SLOTS; ++s) pre[s] = *(const AOL_GLOBAL v4i*)(p0[s] + adv);
     } else {
-      const int last = G.zrow0 + G.Lz - 1;
+      const int last = zrow0 + Lz - 1;
 #pragma unroll
       for (int s = 0; s < SLOTS; ++s) {
-        int gr = min(row[s] + 16 * m, last);
-        if constexpr (WRAP1) {
-          gr = gr < 0 ? gr + S.h : gr;
-          gr = gr >= S.h ? gr - S.h : gr;
-        } else {
-          gr = bpmod(gr, S.h);
-        }
+        // no per-lane branch between the loads: a divergent branch here
+        // would make the compiler's load counts inexact
+        const int gr = bpmod(min(row[s] + 16 * m, last), h);
         pre[s] = *(const AOL_GLOBAL v4i*)(p0[s] + (uint64_t)((int64_t)(gr - row[s]) * pitch));
       }
     }
@@ -255,7 +267,7 @@ struct BandFeed {
   }
 
   // integer form: staged as signed bytes x - 128 (the matrix-core operand)
-  __device__ __forceinline__ void commit(const v4i (&pre)[SLOTS], uint8_t* xs) const {
+  static __device__ __forceinline__ void commit(const v4i (&pre)[SLOTS], const int (&xo)[SLOTS], uint8_t* xs) {
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s)
       *reinterpret_cast<v4i*>(xs + xo[s]) = ELEM == kU8 ? b_to_i8(pre[s]) : pre[s];
@@ -304,7 +316,7 @@ struct BandH {
     astep = gw * pchunks * 16;
     zl = const_cast<uint8_t*>(lds) + S.lds_z + (16 * b0 + n) * S.rpitch;
     zstep = 16 * bstep * S.rpitch;
-    xbuf = 16 * S.xpitch;
+    xbuf = S.xbuf;
     zhalf = S.zhalf;
   }
 
@@ -330,9 +342,10 @@ struct BandH {
     }
   }
 
-  // zm: ring line of step m's first intermediate line
-  __device__ __forceinline__ void run(int m, int zm, int g) const {
-    const uint8_t* xm = xa + (m & 1) * xbuf;
+  // zm: ring line of the step's first intermediate line; par: staging
+  // buffer of the step
+  __device__ __forceinline__ void run(int zm, int par, int g) const {
+    const uint8_t* xm = xa + par * xbuf;
     uint8_t* zrow = zl + (zm + 4 * g) * ES;  // lane's 4 intermediate lines in its ring row
     for (int i = 0; i < nbi; i += NB) {
       v4i a[NB][KM];
@@ -388,76 +401,6 @@ struct BandH {
   }
 };
 
-// Loading waves of one unit: keep D steps of input lines in flight in
-// registers and commit step m+1 into its staging buffer while the compute
-// waves work on step m (from the other buffer); one barrier per step, one at
-// the start (step 0 staged) and one at the end (the unit's LDS free). These
-// waves issue no stores to memory, so their waits on loads count exactly (on
-// gfx9 a wave with loads and stores outstanding can only wait for all of
-// them).
-template <int ELEM, int SLOTS, bool WRAP1, class HP>
-__device__ __forceinline__ void band_feed_unit(const BandFeed<ELEM, SLOTS>& F, const BandStream& S,
-                                               const BandUnitGeo& G, uint8_t* xs, HP& H, int g) {
-  constexpr int D = BandDepth<SLOTS>::value;
-  const int xbuf = 16 * S.xpitch;  // bytes from staging buffer 0 to buffer 1
-  v4i pre[D][SLOTS];
-#pragma unroll
-  for (int k = 0; k < D; ++k) F.template issue<WRAP1>(pre[k], S, G, k);
-  F.commit(pre[0], xs);
-  F.template issue<WRAP1>(pre[0], S, G, D);
-  lds_barrier();  // step 0 staged, the unit's coefficients in place
-  H.load_operands();
-  // Every iteration commits and re-issues one register set, so the loads in
-  // flight at the loop head are the same sets in the same order on entry and
-  // on the back edge. Steps past the unit stage its last line again into a
-  // buffer nobody reads any more. The loop runs whole groups of D steps,
-  // without an exit in between (an exit path would reach the loop head with
-  // other loads in flight).
-  int m0 = 0, zm = 0;
-  for (; m0 + D <= G.M; m0 += D) {
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const int m = m0 + k;
-      const int j = (k + 1) % D;  // a constant once the loop is unrolled
-      F.commit(pre[j], xs + ((m + 1) & 1) * xbuf);
-      F.template issue<WRAP1>(pre[j], S, G, m + 1 + D);
-      H.run(m, zm, g);  // this wave's share of step m's horizontal pass
-      zm = zm + 16 == S.ring ? 0 : zm + 16;
-      lds_barrier();  // step m done with its buffer, step m+1 staged
-    }
-  }
-#pragma unroll
-  for (int k = 0; k + 1 < D; ++k) {
-    if (m0 + k < G.M) {
-      F.commit(pre[(k + 1) % D], xs + ((m0 + k + 1) & 1) * xbuf);
-      H.run(m0 + k, zm, g);
-      zm = zm + 16 == S.ring ? 0 : zm + 16;
-      lds_barrier();
-    }
-  }
-  // nothing of this unit stays in flight into the next one
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-  lds_barrier();  // the compute waves are done with the unit's LDS
-}
-
-// The same for lines that are gathered element by element: no prefetch.
-template <int ELEM, int SLOTS, class HP>
-__device__ __forceinline__ void band_feed_unit_gathered(const BandFeed<ELEM, SLOTS>& F, const BandStream& S,
-                                                        const BandUnitGeo& G, uint8_t* xs, HP& H, int g) {
-  const int xbuf = 16 * S.xpitch;
-  F.stage_gathered(S, G, 0, xs);
-  lds_barrier();  // step 0 staged, the unit's coefficients in place
-  H.load_operands();
-  int zm = 0;
-  for (int m = 0; m < G.M; ++m) {
-    if (m + 1 < G.M) F.stage_gathered(S, G, m + 1, xs + ((m + 1) & 1) * xbuf);
-    H.run(m, zm, g);
-    zm = zm + 16 == S.ring ? 0 : zm + 16;
-    lds_barrier();  // step m done with its buffer, step m+1 staged
-  }
-  lds_barrier();  // the compute waves are done with the unit's LDS
-}
-
 // Stream descriptor and geometry of unit u (of the whole launch: units of
 // one frame, repeated over frames).
 template <int ELEM>
@@ -468,42 +411,192 @@ __device__ __forceinline__ void band_unit(const BandLaunch& L, int u, BandStream
   // by value: kept in scalar registers instead of being re-read from memory
   // after every global store (the compiler cannot rule out aliasing)
   S = load_const(L.streams + U.stream);
-  const cband_t hb = (cband_t)S.hb;
-  const cband_t vb = (cband_t)S.vb;
   const AOL_CONST uint64_t* table = (const AOL_CONST uint64_t*)L.ptr_table;
-  const uint64_t pin = table ? table[2 * S.ptr] : (uint64_t)L.ptrs[2 * S.ptr];
-  const uint64_t pout = table ? table[2 * S.ptr + 1] : (uint64_t)L.ptrs[2 * S.ptr + 1];
-  const int64_t fin = L.ptr_table ? 0 : L.fstride[2 * S.ptr];
-  const int64_t fout = L.ptr_table ? 0 : L.fstride[2 * S.ptr + 1];
+  const uint64_t pin = table ? table[2 * U.ptr] : (uint64_t)L.ptrs[2 * U.ptr];
+  const uint64_t pout = table ? table[2 * U.ptr + 1] : (uint64_t)L.ptrs[2 * U.ptr + 1];
+  const int64_t fin = L.ptr_table ? 0 : L.fstride[2 * U.ptr];
+  const int64_t fout = L.ptr_table ? 0 : L.fstride[2 * U.ptr + 1];
   G.src = (gsrc_t)pin + (int64_t)frame * fin * ES;
   G.dst = (gdst_t)pout + (int64_t)frame * fout * (ELEM == kU8 ? 1 : 4);
-  const int R0x = U.xb * S.xreps, R0y = U.sy * S.seg;
-  const int nRx = min(S.xreps, S.rx - R0x);
-  const int nRy = min(S.seg, S.ry - R0y);
-  G.Lz = vb->q * (nRy - 1) + vb->span;
-  G.zrow0 = vb->q * R0y + vb->s_min;
-  G.M = (G.Lz + 15) >> 4;
-  G.NBV = (vb->p * nRy + 15) >> 4;
-  G.a0 = hb->q * R0x + hb->s_min - hb->delta;
-  G.orow0 = vb->p * R0y;
-  G.ocol0 = hb->p * R0x;
-  G.row_end = min(S.mh, G.orow0 + vb->p * nRy);
-  G.col_end = min(S.mw, G.ocol0 + hb->p * nRx);
-  G.nbh = (hb->p * nRx + 15) >> 4;
+  G.Lz = U.Lz;
+  G.zrow0 = U.zrow0;
+  G.M = U.M;
+  G.NBV = U.NBV;
+  G.a0 = U.a0;
+  G.orow0 = U.orow0;
+  G.ocol0 = U.ocol0;
+  G.row_end = U.row_end;
+  G.col_end = U.col_end;
+  G.nbh = U.nbh;
   G.vec_in = S.vec_in && L.aligned;
   G.vec_out = S.vec_out && L.aligned;
 }
 
-// Vertical block table of one unit: lane B describes vertical block B.
-// Entry: bits 0-15: ring line of its first chunk; 16-23: first
-// fragment; 24-28: block within the period; 29-31: K-steps. Need: the
-// intermediate lines (from the unit's first) its window reaches.
-__device__ __forceinline__ void vblock_entry(cband_t vb, int B, int E, int ring, int Lz, uint32_t& ent, int& need) {
-  const int per = B / vb->nblk, lb = B - per * vb->nblk;
-  const int c0 = vb->chunk0[lb] + per * (vb->q * 16 / E);  // chunks of E intermediate lines
-  ent = (uint32_t)((c0 * E) % ring) | ((uint32_t)vb->frag[lb] << 16) | ((uint32_t)lb << 24) |
-        ((uint32_t)vb->nk[lb] << 29);
-  need = min(Lz, vb->wend[lb] + 16 * per * vb->q);
+// Workgroup's share of the launch: positions [i0, i1) of the unit order.
+__device__ __forceinline__ void band_share(const BandLaunch& L, int& i0, int& i1) {
+  const AOL_CONST int32_t* f = (const AOL_CONST int32_t*)L.first + blockIdx.x;
+  i0 = f[0];
+  i1 = f[1];
+}
+
+__device__ __forceinline__ int band_unit_at(const BandLaunch& L, int i) {
+  return ((const AOL_CONST int32_t*)L.order)[i];
+}
+
+// Stream descriptor of unit u (the loading waves need the next unit's
+// staging offsets before its geometry).
+__device__ __forceinline__ BandStream band_stream_of(const BandLaunch& L, int u) {
+  const int frame = u / L.units_per_frame;
+  const BandUnit U = load_const(L.units + (u - frame * L.units_per_frame));
+  return load_const(L.streams + U.stream);
+}
+
+// The loading waves' read position: the unit and step whose lines the next
+// issue loads, and the lane's chunk addresses in that unit. It runs D steps
+// ahead of the staging and moves on to the workgroup's next unit at the end
+// of one, so a unit's first lines are in flight while the previous one ends.
+// Past the workgroup's last unit it stays on that unit's last line.
+template <int ELEM, int SLOTS>
+struct BandCursor {
+  static constexpr int ES = ELEM == kU8 ? 1 : 2;
+  BandFeed<ELEM, SLOTS> F;
+  int i, i1, m, M, h, zrow0, Lz;  // position in the unit order, end of the workgroup's share
+  int64_t pitch;  // bytes between plane lines
+
+  __device__ __forceinline__ void at(const BandStream& S, const BandUnitGeo& G, int pos, int ltid) {
+    F.addresses(S, G, ltid);
+    i = pos;
+    m = 0;
+    M = G.M;
+    h = S.h;
+    zrow0 = G.zrow0;
+    Lz = G.Lz;
+    pitch = S.in_pitch * ES;
+  }
+  __device__ __forceinline__ void issue(v4i (&pre)[SLOTS]) const { F.issue(pre, h, pitch, zrow0, Lz, m); }
+  __device__ __forceinline__ void advance(const BandLaunch& L, int ltid) {
+    ++m;
+    if (m == M && i + 1 < i1) {  // uniform; no loads on this path
+      BandStream S;
+      BandUnitGeo G;
+      band_unit<ELEM>(L, band_unit_at(L, i + 1), S, G);
+      at(S, G, i + 1, ltid);
+    }
+  }
+};
+
+// Loading waves (whole chunks): one pipeline over all the workgroup's units.
+// Each step commits the next step's lines (maybe the next unit's first) into
+// the staging buffer the compute waves are not reading, issues the loads D
+// steps ahead, takes its share of the horizontal pass, and meets the
+// compute waves at the step's barrier; a unit adds a barrier at its end (its
+// LDS free) and one at the next unit's start (its coefficients in place).
+// The staging buffer of a step is the parity of its index in the
+// workgroup's sequence of steps. These waves issue no stores to memory and
+// every iteration commits and re-issues one register set, so the loads in
+// flight at the loop head are the same sets in the same order on entry and
+// on the back edge, and their waits count exactly (on gfx9 a wave with loads
+// and stores outstanding can only wait for all of them).
+template <int ELEM, int SLOTS, class HP>
+__device__ __forceinline__ void band_load_pipeline(const BandLaunch& L, uint8_t* lds, int tid, int wave, int lane) {
+  constexpr int D = BandDepth<SLOTS>::value;
+  const int g = lane >> 4;
+  int i, i1;  // position in the unit order, end of the workgroup's share
+  band_share(L, i, i1);
+  BandStream S;
+  BandUnitGeo G;
+  band_unit<ELEM>(L, band_unit_at(L, i), S, G);
+  BandCursor<ELEM, SLOTS> C;
+  C.i1 = i1;
+  C.at(S, G, i, tid);
+  int xo[SLOTS];
+  BandFeed<ELEM, SLOTS>::offsets(S, tid, xo);
+  HP H;
+  H.setup(S, G, lds, wave, lane);
+  v4i pre[D][SLOTS];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    C.issue(pre[k]);
+    C.advance(L, tid);
+  }
+  BandFeed<ELEM, SLOTS>::commit(pre[0], xo, lds + S.lds_x);  // step 0: buffer 0
+  C.issue(pre[0]);
+  C.advance(L, tid);
+  lds_barrier();  // step 0 staged, the unit's coefficients in place
+  H.load_operands();
+  int m = 0, t = 0, zm = 0;  // step within the unit, step within the workgroup, ring line
+  bool live = true;          // uniform: units left
+  // Whole groups of D steps (the register set of a step is a constant once
+  // unrolled). The loop is left only at the end of a group: an exit from
+  // inside would reach the loop head, as the compiler lays it out, with
+  // another set newest and make every wait there drain the prefetch. After
+  // the last unit the group finishes without barriers or compute.
+  for (;;) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const int j = (k + 1) % D;
+      const bool last = m + 1 == G.M;  // uniform
+      if (last && i + 1 < i1)  // the next step is the next unit's first
+        BandFeed<ELEM, SLOTS>::offsets(band_stream_of(L, band_unit_at(L, i + 1)), tid, xo);
+      BandFeed<ELEM, SLOTS>::commit(pre[j], xo, lds + S.lds_x + ((t + 1) & 1) * S.xbuf);
+      C.issue(pre[j]);
+      C.advance(L, tid);
+      if (live) {
+        H.run(zm, t & 1, g);  // this wave's share of step m's horizontal pass
+        zm = zm + 16 == S.ring ? 0 : zm + 16;
+        lds_barrier();  // step m done with its buffer, the next step staged
+        if (last) {
+          lds_barrier();  // the compute waves are done with the unit's LDS
+          ++i;
+          live = i < i1;
+          if (live) {
+            band_unit<ELEM>(L, band_unit_at(L, i), S, G);
+            H.setup(S, G, lds, wave, lane);
+            m = -1;
+            zm = 0;
+            lds_barrier();  // the unit's coefficients in place (its step 0 was staged before)
+            H.load_operands();
+          }
+        }
+      }
+      ++m;
+      ++t;
+    }
+    if (!live) break;
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): nothing left in flight
+}
+
+// Loading waves for lines that are gathered element by element: no
+// prefetch, unit by unit (a call, which waits for every load it issues).
+template <int ELEM, int SLOTS, class HP>
+__device__ __forceinline__ void band_load_gathered(const BandLaunch& L, uint8_t* lds, int tid, int wave, int lane) {
+  const int g = lane >> 4;
+  int t0 = 0;  // the unit's first step within the workgroup (staging buffer parity)
+  int i0, i1;
+  band_share(L, i0, i1);
+  for (int i = i0; i < i1; ++i) {
+    BandStream S;
+    BandUnitGeo G;
+    band_unit<ELEM>(L, band_unit_at(L, i), S, G);
+    BandFeed<ELEM, SLOTS> F;
+    F.setup(S, G, tid);
+    HP H;
+    H.setup(S, G, lds, wave, lane);
+    uint8_t* xs = lds + S.lds_x;
+    F.stage_gathered(S, G, 0, xs + (t0 & 1) * S.xbuf);
+    lds_barrier();  // step 0 staged, the unit's coefficients in place
+    H.load_operands();
+    int zm = 0;
+    for (int m = 0; m < G.M; ++m) {
+      if (m + 1 < G.M) F.stage_gathered(S, G, m + 1, xs + ((t0 + m + 1) & 1) * S.xbuf);
+      H.run(zm, (t0 + m) & 1, g);
+      zm = zm + 16 == S.ring ? 0 : zm + 16;
+      lds_barrier();  // step m done with its buffer, step m+1 staged
+    }
+    lds_barrier();  // the compute waves are done with the unit's LDS
+    t0 += G.M;
+  }
 }
 
 // GATHER: an instance for launches with a line that is not made of whole
@@ -526,28 +619,22 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
 
   // The two roles loop over the same units separately, so that the loading
   // waves' code never has a store in flight.
+  int i0, i1;
+  band_share(L, i0, i1);
   if (loader) {
-    for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
-      BandStream S;
-      BandUnitGeo G;
-      band_unit<ELEM>(L, u, S, G);
-      uint8_t* xs = lds + S.lds_x;
-      BandFeed<ELEM, SLOTS> F;
-      F.setup(S, G, tid);
-      BandH<ELEM, split, KM, 1> H;  // one block at a time: the prefetch holds the registers
-      H.setup(S, G, lds, wave, lane);
-      if constexpr (GATHER) band_feed_unit_gathered<ELEM, SLOTS>(F, S, G, xs, H, g);
-      else if (G.zrow0 >= -S.h && G.zrow0 + G.Lz <= 2 * S.h) band_feed_unit<ELEM, SLOTS, true>(F, S, G, xs, H, g);
-      else band_feed_unit<ELEM, SLOTS, false>(F, S, G, xs, H, g);
-    }
+    if (i0 >= i1) return;
+    // one block at a time in the horizontal pass: the prefetch holds the registers
+    if constexpr (GATHER) band_load_gathered<ELEM, SLOTS, BandH<ELEM, split, KM, 1>>(L, lds, tid, wave, lane);
+    else band_load_pipeline<ELEM, SLOTS, BandH<ELEM, split, KM, 1>>(L, lds, tid, wave, lane);
     return;
   }
 
   cband_t cur_hb = nullptr;
-  for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
+  int t0 = 0;  // the unit's first step within the workgroup (staging buffer parity)
+  for (int i = i0; i < i1; ++i) {
     BandStream S;
     BandUnitGeo G;
-    band_unit<ELEM>(L, u, S, G);
+    band_unit<ELEM>(L, band_unit_at(L, i), S, G);
     const cband_t hb = (cband_t)S.hb;
     const cband_t vb = (cband_t)S.vb;
     uint8_t* zs = lds + S.lds_z;
@@ -568,6 +655,8 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
         for (int i = ctid; i < hb->nblk * 16; i += NW * 64) ((int*)bh)[i] = hb->bias[i];
         for (int i = ctid; i < vb->nblk * 16; i += NW * 64) ((int*)bv)[i] = vb->bias[i];
       }
+      const AOL_GLOBAL uint32_t* gt = (const AOL_GLOBAL uint32_t*)S.vtab;
+      for (int i = ctid; i < 2 * 64; i += NW * 64) ((uint32_t*)(lds + S.lds_vt))[i] = gt[i];
     }
     if constexpr (ELEM != kU8) {
       // float ring starts at zero so the zero taps of a block's padding never meet a NaN
@@ -580,19 +669,12 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
     // blocks (lane B: block B)
     BandH<ELEM, split, KM, NB> H;
     H.setup(S, G, lds, wave, lane);
-    uint32_t vtbl = 0;
-    int vneed = 0;
-    for (int b = 0; b < G.NBV; ++b) {  // scalar reads of the descriptor, one lane written per block
-      uint32_t ent;
-      int need;
-      vblock_entry(vb, b, E, S.ring, G.Lz, ent, need);
-      vtbl = lane == b ? ent : vtbl;
-      vneed = lane == b ? need : vneed;
-    }
+    uint32_t vtbl = 0;  // lane B: vertical block B (read after the unit's first barrier)
+    int vneed = 0;      // and the intermediate lines its window reaches
     const int vz = vb->zfrag;
     const uint8_t* fvl = fv + lane * 16;
     int B = 0;  // next vertical block
-    int needB = __builtin_amdgcn_readlane(vneed, 0);
+    int needB = 0;
 
     // ---- vertical blocks whose window lies in the first `have` intermediate lines
     auto vpass = [&](int have) {
@@ -682,17 +764,24 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
 
     lds_barrier();  // step 0 staged, coefficients in place
     H.load_operands();
+    {
+      const uint32_t* vt = reinterpret_cast<const uint32_t*>(lds + S.lds_vt);
+      vtbl = lane < G.NBV ? vt[lane] : 0u;
+      vneed = lane < G.NBV ? min(G.Lz, (int)vt[64 + lane]) : 0;
+      needB = __builtin_amdgcn_readlane(vneed, 0);
+    }
     int zm = 0;     // ring line of step m's first intermediate line
     for (int m = 0; m < G.M; ++m) {
       // vertical blocks complete with step m-1's lines (the horizontal pass of
       // step m writes other ring lines meanwhile)
       vpass(min(G.Lz, 16 * m));
-      H.run(m, zm, g);  // this wave's share of step m's horizontal pass
+      H.run(zm, (t0 + m) & 1, g);  // this wave's share of step m's horizontal pass
       zm = zm + 16 == S.ring ? 0 : zm + 16;
       lds_barrier();  // step m's intermediate lines written, step m+1 staged
     }
     vpass(G.Lz);    // the rest of the unit's vertical blocks
     lds_barrier();  // the unit's LDS free
+    t0 += G.M;
   }
 }
 

@@ -4,6 +4,9 @@
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
+#include <numeric>
+#include <queue>
 
 namespace aol {
 
@@ -31,6 +34,15 @@ aol_status build_filter_bands(const FilterHost& hf, const FilterHost& vf, int el
     span = std::max(span, 16 * m - E * vb.chunk0[lb] - 16 * per * vb.q);
   }
   const int ring = (span + 16 + 15) / 16 * 16;  // whole steps of 16 lines
+  std::vector<uint32_t> vtab(2 * kBandVBlocks);
+  for (int B = 0; B < kBandVBlocks; ++B) {
+    const int per = B / vb.nblk, lb = B % vb.nblk;
+    const int c0 = vb.chunk0[lb] + per * (vb.q * 16 / E);  // chunks of E intermediate lines
+    vtab[B] = (uint32_t)((c0 * E) % ring) | ((uint32_t)vb.frag[lb] << 16) | ((uint32_t)lb << 24) |
+              ((uint32_t)vb.nk[lb] << 29);
+    vtab[kBandVBlocks + B] = (uint32_t)(vb.wend[lb] + 16 * per * vb.q);
+  }
+  if ((st = out.d_vtab.upload(vtab.data(), vtab.size() * sizeof(uint32_t)))) return st;
   out.elem = elem;
   out.hb = hb;
   out.vb = vb;
@@ -44,22 +56,34 @@ aol_status build_filter_bands(const FilterHost& hf, const FilterHost& vf, int el
   return AOL_OK;
 }
 
-static int layout(const FilterBands& fb, int nbh, int nch, BandStream& S) {
+// LDS layout of one stream: two staging buffers of xbuf bytes at offset 0,
+// then the coefficient fragments and biases, then the ring.
+static int layout(const FilterBands& fb, int nbh, int nch, int xbuf, BandStream& S) {
   const int es = fb.elem == kU8 ? 1 : 2;
   S.ring = fb.ring;
   S.rpitch = fb.ring * es + 16;  // odd multiple of 16 bytes between ring rows
   if ((S.rpitch / 16) % 2 == 0) S.rpitch += 16;
   S.xpitch = nch * 16;
   if ((S.xpitch / 16) % 2 == 0) S.xpitch += 16;
-  S.lds_fh = 0;
+  S.xbuf = std::max(xbuf, 16 * S.xpitch);
+  S.lds_x = 0;
+  S.lds_fh = 2 * S.xbuf;
   S.lds_fv = S.lds_fh + fb.hb.nfrag * kLanes * 16;
   S.lds_bh = S.lds_fv + fb.vb.nfrag * kLanes * 16;
   S.lds_bv = S.lds_bh + fb.hb.nblk * 16 * 4;
-  S.lds_x = (S.lds_bv + fb.vb.nblk * 16 * 4 + 15) / 16 * 16;
-  S.lds_z = S.lds_x + 32 * S.xpitch;  // two staging buffers of 16 lines
+  S.lds_vt = S.lds_bv + fb.vb.nblk * 16 * 4;
+  S.lds_z = (S.lds_vt + 2 * kBandVBlocks * 4 + 15) / 16 * 16;
   const int zbytes = nbh * 16 * S.rpitch;
   S.zhalf = fb.elem == kU8 ? 0 : zbytes;
   return S.lds_z + zbytes * (fb.elem == kU8 ? 1 : 2);
+}
+
+int band_share_staging(BandStream* const* streams, const FilterBands* const* fbs, int n) {
+  int xbuf = 0;
+  for (int i = 0; i < n; ++i) xbuf = std::max(xbuf, 16 * streams[i]->xpitch);
+  int total = 0;
+  for (int i = 0; i < n; ++i) total = std::max(total, layout(*fbs[i], streams[i]->nbh, streams[i]->nch, xbuf, *streams[i]));
+  return total;
 }
 
 aol_status build_band_stream(const FilterBands& fb, int64_t h, int64_t w, int64_t in_pitch, int64_t out_pitch,
@@ -85,7 +109,7 @@ aol_status build_band_stream(const FilterBands& fb, int64_t h, int64_t w, int64_
     std::tie(nbh, nch) = chunks(xr);
     BandStream T;
     memset(&T, 0, sizeof T);
-    total = layout(fb, nbh, nch, T);
+    total = layout(fb, nbh, nch, 0, T);
     const bool fits = total <= lds_budget && 16 * nch <= kBandMaxSlots * kBandLoadThreads;
     if (fits || xreps > 0 || xr <= 16) {
       S = T;
@@ -119,9 +143,69 @@ aol_status build_band_stream(const FilterBands& fb, int64_t h, int64_t w, int64_
   S.vb = (const AxisBand*)fb.d_vb.ptr;
   S.hfrag = fb.d_hfrag.ptr;
   S.vfrag = fb.d_vfrag.ptr;
+  S.vtab = fb.d_vtab.ptr;
   *lds_bytes = total;
   *slots = sl;
   return AOL_OK;
+}
+
+BandUnit band_make_unit(const BandStream& S, const FilterBands& fb, int stream, int xb, int sy) {
+  const AxisBand& hb = fb.hb;
+  const AxisBand& vb = fb.vb;
+  BandUnit U;
+  memset(&U, 0, sizeof U);
+  const int R0x = xb * S.xreps, R0y = sy * S.seg;
+  const int nRx = std::min(S.xreps, S.rx - R0x);
+  const int nRy = std::min(S.seg, S.ry - R0y);
+  U.stream = stream;
+  U.ptr = S.ptr;
+  U.Lz = vb.q * (nRy - 1) + vb.span;
+  U.zrow0 = vb.q * R0y + vb.s_min;
+  U.M = (U.Lz + 15) >> 4;
+  U.NBV = (vb.p * nRy + 15) >> 4;
+  U.a0 = hb.q * R0x + hb.s_min - hb.delta;
+  U.orow0 = vb.p * R0y;
+  U.ocol0 = hb.p * R0x;
+  U.row_end = std::min(S.mh, U.orow0 + vb.p * nRy);
+  U.col_end = std::min(S.mw, U.ocol0 + hb.p * nRx);
+  U.nbh = (hb.p * nRx + 15) >> 4;
+  return U;
+}
+
+int64_t band_unit_cost(const BandStream& S, const AxisBand& vb, int sy) {
+  const int nRy = std::min(S.seg, S.ry - sy * S.seg);
+  const int Lz = vb.q * (nRy - 1) + vb.span;
+  const int64_t steps = (Lz + 15) / 16;
+  // cycles of one workgroup, roughly: per step a fixed part and a part per
+  // staged chunk of the line; per unit its set-up and last vertical blocks
+  return steps * (900 + 12 * (int64_t)S.nch) + 7000;
+}
+
+void band_balance(const std::vector<int64_t>& cost, int grid, std::vector<int32_t>& order,
+                  std::vector<int32_t>& first) {
+  const int n = (int)cost.size();
+  std::vector<int32_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  typedef std::pair<int64_t, int> Load;  // (cost so far, workgroup)
+  std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+  for (int g = 0; g < grid; ++g) heap.push({0, g});
+  std::vector<std::vector<int32_t>> share(grid);
+  for (int u : idx) {
+    const Load l = heap.top();
+    heap.pop();
+    share[l.second].push_back(u);
+    heap.push({l.first + cost[u], l.second});
+  }
+  order.clear();
+  order.reserve(n);
+  first.assign(grid + 1, 0);
+  for (int g = 0; g < grid; ++g) {
+    std::sort(share[g].begin(), share[g].end());  // in unit order: streams (filters) stay together
+    first[g] = (int32_t)order.size();
+    order.insert(order.end(), share[g].begin(), share[g].end());
+  }
+  first[grid] = n;
 }
 
 }  // namespace aol

@@ -18,7 +18,14 @@ struct FilterBands {
   int kmax = 0;       // largest K-step count of a block of either axis
   bool split = false;
   DeviceBuf d_hb, d_vb, d_hfrag, d_vfrag;
+  // Vertical block table, copied into LDS with the coefficients: entry B
+  // (bits 0-15: ring line of the block's first chunk; 16-23: first
+  // fragment; 24-28: block within the period; 29-31: K-steps), then the
+  // intermediate lines (from a unit's first) block B's window reaches.
+  DeviceBuf d_vtab;
 };
+
+constexpr int kBandVBlocks = 64;  // vertical blocks per unit at most (one per lane)
 
 aol_status build_filter_bands(const FilterHost& hf, const FilterHost& vf, int elem, bool force_split, FilterBands& out);
 
@@ -27,6 +34,24 @@ aol_status build_filter_bands(const FilterHost& hf, const FilterHost& vf, int el
 // lds_budget; returns AOL_ERR_UNSUPPORTED when not even one period fits.
 aol_status build_band_stream(const FilterBands& fb, int64_t h, int64_t w, int64_t in_pitch, int64_t out_pitch,
                              int xreps, int seg, int lds_budget, BandStream& S, int* lds_bytes, int* slots);
+
+// Lays out the streams of one launch around shared staging buffers (sized
+// for the widest) and returns the LDS bytes a workgroup needs for any of them.
+int band_share_staging(BandStream* const* streams, const FilterBands* const* fbs, int n);
+
+// The unit of column band xb and segment sy of stream `stream` (S built by
+// build_band_stream).
+BandUnit band_make_unit(const BandStream& S, const FilterBands& fb, int stream, int xb, int sy);
+
+// Estimated cost of the unit of segment sy of a stream (arbitrary units).
+int64_t band_unit_cost(const BandStream& S, const AxisBand& vb, int sy);
+
+// Assigns units of the given costs to `grid` workgroups, longest first, each
+// to the least loaded workgroup so far. order: the unit ids grouped by
+// workgroup (each group in id order); first: the start of each group in
+// order (grid + 1 entries).
+void band_balance(const std::vector<int64_t>& cost, int grid, std::vector<int32_t>& order,
+                  std::vector<int32_t>& first);
 
 hipError_t set_pointers_launch(void** table, const void* const* ptrs, int n, hipStream_t stream);
 

@@ -49,6 +49,7 @@ struct aol_batch_plan {
   size_t lds = 0;
   size_t unit_capacity = 0;
   DeviceBuf d_streams, d_units, d_table;
+  DeviceBuf d_order, d_first;  // balanced unit order: unit_capacity and unit_capacity + 1 entries
   bool pointers_set = false;
   std::string cache_path, key, sched_json;
 };
@@ -61,31 +62,43 @@ struct aol_graph {
 static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
   std::vector<BandStream> streams(bp->n);
   int lds = 0, slots = 0;
-  std::vector<std::pair<int64_t, BandUnit>> work;
+  // The streams share staging buffers sized for the widest, so the launch may
+  // need more LDS than any one stream: narrow the column bands until it fits.
+  for (int budget = sc.budget;;) {
+    slots = 0;
+    for (int i = 0; i < bp->n; ++i) {
+      const aol_stream_desc& d = bp->desc[i];
+      int l = 0, sl = 0;
+      aol_status st = build_band_stream(bp->bands[bp->filt[i]], d.height, d.width, d.in_pitch, d.out_pitch, 0, sc.seg,
+                                        budget, streams[i], &l, &sl);
+      if (st) return st;
+      streams[i].ptr = i;
+      slots = std::max(slots, sl);
+    }
+    std::vector<BandStream*> sp;
+    std::vector<const FilterBands*> fp;
+    for (int i = 0; i < bp->n; ++i) {
+      sp.push_back(&streams[i]);
+      fp.push_back(&bp->bands[bp->filt[i]]);
+    }
+    lds = band_share_staging(sp.data(), fp.data(), bp->n);
+    if (lds <= sc.budget) break;
+    budget -= std::max(lds - sc.budget, 1024);
+    if (budget < 8 * 1024) return fail(AOL_ERR_UNSUPPORTED, "batch streams do not fit %d bytes of LDS", sc.budget);
+  }
+  // units in stream order (so a workgroup's units mostly share a filter),
+  // assigned to workgroups by their estimated cost
+  std::vector<BandUnit> units;
+  std::vector<int64_t> cost;
   for (int i = 0; i < bp->n; ++i) {
-    const aol_stream_desc& d = bp->desc[i];
-    int l = 0, sl = 0;
-    aol_status st = build_band_stream(bp->bands[bp->filt[i]], d.height, d.width, d.in_pitch, d.out_pitch, 0, sc.seg,
-                                      sc.budget, streams[i], &l, &sl);
-    if (st) return st;
-    streams[i].ptr = i;
-    lds = std::max(lds, l);
-    slots = std::max(slots, sl);
     const BandStream& S = streams[i];
     const int nxb = (S.rx + S.xreps - 1) / S.xreps, nsy = (S.ry + S.seg - 1) / S.seg;
     for (int sy = 0; sy < nsy; ++sy)
       for (int xb = 0; xb < nxb; ++xb) {
-        const int64_t rows = std::min<int64_t>(S.seg, S.ry - (int64_t)sy * S.seg);
-        const int64_t cols = std::min<int64_t>(S.xreps, S.rx - (int64_t)xb * S.xreps);
-        work.push_back({rows * cols * bp->hf[i].q * bp->vf[i].q, BandUnit{i, xb, sy, 0}});
+        units.push_back(band_make_unit(S, bp->bands[bp->filt[i]], i, xb, sy));
+        cost.push_back(band_unit_cost(S, bp->bands[bp->filt[i]].vb, sy));
       }
   }
-  // largest units first, so the strided persistent walk ends with small ones;
-  // ties keep streams (and so filters) together
-  std::stable_sort(work.begin(), work.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
-  std::vector<BandUnit> units;
-  units.reserve(work.size());
-  for (auto& w : work) units.push_back(w.second);
   int wg = 0;
   hipError_t e = band_prepare(bp->elem, slots, bp->split, bp->kmax, (size_t)lds, &wg);
   if (e != hipSuccess) return hip_fail(e, "band kernel attributes");
@@ -103,11 +116,19 @@ static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
   if ((e = hipMemcpy(bp->d_units.ptr, units.data(), sizeof(BandUnit) * units.size(), hipMemcpyHostToDevice)) !=
       hipSuccess)
     return hip_fail(e, "hipMemcpy");
+  const int grid = (int)std::min<int64_t>((int64_t)wg * cus, (int64_t)units.size());
+  std::vector<int32_t> order, first;
+  band_balance(cost, grid, order, first);
+  if ((e = hipMemcpy(bp->d_order.ptr, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(bp->d_first.ptr, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice)) !=
+          hipSuccess)
+    return hip_fail(e, "hipMemcpy");
   bp->streams = std::move(streams);
   bp->units = std::move(units);
   bp->lds = (size_t)lds;
   bp->slots = slots;
-  bp->grid = (int)std::min<int64_t>((int64_t)wg * cus, (int64_t)bp->units.size());
+  bp->grid = grid;
   bp->sched = sc;
   char buf[160];
   snprintf(buf, sizeof buf, "{\"seg\": %d, \"lds_budget\": %d, \"units\": %d, \"grid\": %d, \"lds\": %d}",
@@ -126,6 +147,8 @@ static aol_status batch_launch(aol_batch_plan* bp, hipStream_t stream) {
   L.total_units = (int32_t)bp->units.size();
   L.aligned = 1;  // checked by aol_batch_set_pointers
   L.ptr_table = (void* const*)bp->d_table.ptr;
+  L.order = (const int32_t*)bp->d_order.ptr;
+  L.first = (const int32_t*)bp->d_first.ptr;
   bool gather = false;
   for (const BandStream& S : bp->streams) gather = gather || !S.vec_in;
   hipError_t e = band_launch(bp->elem, bp->slots, bp->split, bp->kmax, gather, L, bp->grid, bp->lds, stream);
@@ -282,6 +305,8 @@ aol_status aol_batch_plan_create(int32_t n_streams, const aol_stream_desc* strea
   }
   st = bp->d_streams.alloc(sizeof(BandStream) * (size_t)n_streams);
   if (!st) st = bp->d_units.alloc(sizeof(BandUnit) * bp->unit_capacity);
+  if (!st) st = bp->d_order.alloc(sizeof(int32_t) * bp->unit_capacity);
+  if (!st) st = bp->d_first.alloc(sizeof(int32_t) * (bp->unit_capacity + 1));
   if (!st) st = batch_build(bp, sc);
   if (!st) st = bp->d_table.alloc(sizeof(void*) * 2 * (size_t)n_streams);
   if (st) {

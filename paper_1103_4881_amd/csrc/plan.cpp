@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <memory>
 #include <climits>
 #include <cstdarg>
 #include <cstdio>
@@ -268,6 +269,15 @@ struct aol_plan {
   FilterBands fbands;
   BandStream bstreams[kMaxPlanes];
   DeviceBuf d_bstreams, d_bunits;
+  std::vector<int64_t> bcost;  // estimated cost of each unit of one frame
+  // Balanced unit order per frame count launched so far. Kept until the plan
+  // is destroyed: a graph that captured a launch copies from the host arrays.
+  struct BandSched {
+    int frames = 0;
+    std::vector<int32_t> order, first;
+    DeviceBuf d_order, d_first;
+  };
+  std::vector<std::unique_ptr<BandSched>> bsched;
   bool split = false;
   DeviceBuf d_hb, d_vb, d_hfrag, d_vfrag;
 };
@@ -384,6 +394,7 @@ static aol_status plan_build_band(aol_plan* pl, int xreps, int seg) {
   if (st) return st == AOL_ERR_UNSUPPORTED ? AOL_OK : st;
   int lds = 0, slots = 0;
   std::vector<BandUnit> units;
+  std::vector<int64_t> costs;
   for (int i = 0; i < pl->n_planes; ++i) {
     int l = 0, sl = 0;
     st = build_band_stream(fb, pl->planes[i].height, pl->planes[i].width, pl->planes[i].in_pitch,
@@ -395,7 +406,20 @@ static aol_status plan_build_band(aol_plan* pl, int xreps, int seg) {
     const BandStream& S = pl->bstreams[i];
     const int nxb = (S.rx + S.xreps - 1) / S.xreps, nsy = (S.ry + S.seg - 1) / S.seg;
     for (int sy = 0; sy < nsy; ++sy)
-      for (int xb = 0; xb < nxb; ++xb) units.push_back(BandUnit{i, xb, sy, 0});
+      for (int xb = 0; xb < nxb; ++xb) {
+        units.push_back(band_make_unit(S, fb, i, xb, sy));
+        costs.push_back(band_unit_cost(S, fb.vb, sy));
+      }
+  }
+  {
+    std::vector<BandStream*> sp;
+    std::vector<const FilterBands*> fp;
+    for (int i = 0; i < pl->n_planes; ++i) {
+      sp.push_back(&pl->bstreams[i]);
+      fp.push_back(&fb);
+    }
+    lds = band_share_staging(sp.data(), fp.data(), pl->n_planes);
+    if (lds > kBandLdsBudget) return AOL_OK;
   }
   int wg = 0;
   hipError_t e = band_prepare(pl->elem, slots, fb.split, fb.kmax, (size_t)lds, &wg);
@@ -412,6 +436,8 @@ static aol_status plan_build_band(aol_plan* pl, int xreps, int seg) {
   pl->d_bstreams = std::move(ds);
   pl->d_bunits = std::move(du);
   pl->bunits = (int)units.size();
+  pl->bcost = std::move(costs);
+  pl->bsched.clear();
   pl->bslots = slots;
   pl->blds = (size_t)lds;
   pl->bgrid = wg * cus;
@@ -610,6 +636,32 @@ static aol_status run_fused(aol_plan* plan, int32_t n_frames, const void* const*
     bool gather = !aligned;
     for (int i = 0; i < plan->n_planes; ++i) gather = gather || !plan->bstreams[i].vec_in;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(L.total_units, plan->bgrid));
+    // the balanced unit order for this frame count (built and copied to the
+    // device on the stream at the first launch with it)
+    aol_plan::BandSched* sc = nullptr;
+    for (auto& x : plan->bsched)
+      if (x->frames == n_frames) sc = x.get();
+    if (!sc) {
+      auto ns = std::make_unique<aol_plan::BandSched>();
+      ns->frames = n_frames;
+      std::vector<int64_t> cost((size_t)L.total_units);
+      for (int f = 0; f < n_frames; ++f)
+        std::copy(plan->bcost.begin(), plan->bcost.end(), cost.begin() + (size_t)f * plan->bunits);
+      band_balance(cost, grid, ns->order, ns->first);
+      aol_status st = ns->d_order.alloc(sizeof(int32_t) * ns->order.size());
+      if (!st) st = ns->d_first.alloc(sizeof(int32_t) * ns->first.size());
+      if (st) return st;
+      hipError_t e = hipMemcpyAsync(ns->d_order.ptr, ns->order.data(), sizeof(int32_t) * ns->order.size(),
+                                    hipMemcpyHostToDevice, stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(ns->d_first.ptr, ns->first.data(), sizeof(int32_t) * ns->first.size(),
+                           hipMemcpyHostToDevice, stream);
+      if (e != hipSuccess) return hip_fail(e, "unit order upload");
+      sc = ns.get();
+      plan->bsched.push_back(std::move(ns));
+    }
+    L.order = (const int32_t*)sc->d_order.ptr;
+    L.first = (const int32_t*)sc->d_first.ptr;
     hipError_t e = band_launch(plan->elem, plan->bslots, plan->fbands.split, plan->fbands.kmax, gather, L, grid,
                                plan->blds, stream);
     if (e != hipSuccess) return hip_fail(e, "band kernel launch");
