@@ -144,10 +144,13 @@ aol_status aol_plan_set_tile(aol_plan* plan, int32_t tile_rx, int32_t tile_ry);
 /* Band schedule (the default for every plan that fits it): a workgroup owns a
  * column band of band_reps repetitions (0: the widest that fits a compute
  * unit, normally the full width) and streams segments of seg_reps
- * repetitions (0: about 256 input lines) down the plane, keeping the
- * intermediate in an LDS ring. Multiples of 16. Selecting a band re-selects
- * the band kernel after aol_plan_set_tile. AOL_ERR_UNSUPPORTED if the band
- * does not fit. Results are identical for every schedule. */
+ * repetitions down the plane, keeping the intermediate in an LDS ring.
+ * seg_reps 0: chosen at the first launch with a given frame count (the
+ * longest of about 1024 ... 64 input lines that leaves every workgroup a few
+ * units; that launch copies the schedule to the device on its stream).
+ * Multiples of 16. Selecting a band re-selects the band kernel after
+ * aol_plan_set_tile. AOL_ERR_UNSUPPORTED if the band does not fit. Results
+ * are identical for every schedule. */
 aol_status aol_plan_set_band(aol_plan* plan, int32_t band_reps, int32_t seg_reps);
 
 /* Order in which each workgroup walks its contiguous run of tiles inside a

@@ -45,6 +45,7 @@
 namespace aol {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
@@ -356,43 +357,55 @@ struct BandH {
         for (int k = 0; k < KM; ++k)
           if (k == 0 || k < nk) a[j][k] = *reinterpret_cast<const v4i*>(xm + ii * astep + 64 * k);
       }
+      // all the products first (a missing block repeats the last one and
+      // is not written), with no branch between them
+      v4i acc[NB], acch[SPLIT ? NB : 1];
+      v4f accf[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        acc[j] = bq;
+        if constexpr (SPLIT) acch[j] = v4i{0, 0, 0, 0};
+        accf[j] = v4f{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (k > 0 && k >= nk) break;  // uniform: the position's own K-steps only
+        v4i blo, bhi;
+        if constexpr (CACHE) {
+          blo = bf[k];
+          if constexpr (SPLIT) bhi = bfh[k];
+        } else if constexpr (SPLIT) {
+          blo = *reinterpret_cast<const v4i*>(fl + (2 * k) * 1024);
+          bhi = *reinterpret_cast<const v4i*>(fl + (2 * k + 1) * 1024);
+        } else {
+          blo = *reinterpret_cast<const v4i*>(fl + k * 1024);
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          if constexpr (ELEM == kU8) {
+            acc[j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], blo, acc[j], 0, 0, 0);
+            if constexpr (SPLIT) acch[j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], bhi, acch[j], 0, 0, 0);
+          } else {
+            accf[j] = b_mfma16<ELEM>(a[j][k], blo, accf[j]);
+          }
+        }
+      }
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         if (j > 0 && i + j >= nbi) break;
         uint8_t* zp = zrow + (i + j) * zstep;
         if constexpr (ELEM == kU8) {
-          v4i acc = bq, acch = {0, 0, 0, 0};
-#pragma unroll
-          for (int k = 0; k < KM; ++k) {
-            if (k > 0 && k >= nk) break;  // uniform: the position's own K-steps only
-            if constexpr (CACHE) {
-              acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], bf[k], acc, 0, 0, 0);
-              if constexpr (SPLIT) acch = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], bfh[k], acch, 0, 0, 0);
-            } else if constexpr (SPLIT) {
-              const v4i lo = *reinterpret_cast<const v4i*>(fl + (2 * k) * 1024);
-              const v4i hi = *reinterpret_cast<const v4i*>(fl + (2 * k + 1) * 1024);
-              acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], lo, acc, 0, 0, 0);
-              acch = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], hi, acch, 0, 0, 0);
-            } else {
-              acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], *reinterpret_cast<const v4i*>(fl + k * 1024), acc, 0, 0, 0);
-            }
-          }
-          if constexpr (SPLIT) acc = acc + acch * 128;
+          v4i r = acc[j];
+          if constexpr (SPLIT) r = r + acch[j] * 128;
           // kept as signed bytes z - 128, the vertical pass's operand
-          *reinterpret_cast<uint32_t*>(zp) = b_quant4(acc, 0) ^ 0x80808080u;
+          *reinterpret_cast<uint32_t*>(zp) = b_quant4(r, 0) ^ 0x80808080u;
         } else {
-          v4f acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int k = 0; k < KM; ++k) {
-            if (k > 0 && k >= nk) break;
-            if constexpr (CACHE) acc = b_mfma16<ELEM>(a[j][k], bf[k], acc);
-            else acc = b_mfma16<ELEM>(a[j][k], *reinterpret_cast<const v4i*>(fl + k * 1024), acc);
-          }
+          const v4f r = accf[j];
           // hi/lo pair: hi = round(z), lo = round(z - hi)
-          const uint32_t h01 = b_pack2<ELEM>(acc[0], acc[1]);
-          const uint32_t h23 = b_pack2<ELEM>(acc[2], acc[3]);
-          const uint32_t l01 = b_pack2<ELEM>(acc[0] - b_lo16<ELEM>(h01), acc[1] - b_hi16<ELEM>(h01));
-          const uint32_t l23 = b_pack2<ELEM>(acc[2] - b_lo16<ELEM>(h23), acc[3] - b_hi16<ELEM>(h23));
+          const uint32_t h01 = b_pack2<ELEM>(r[0], r[1]);
+          const uint32_t h23 = b_pack2<ELEM>(r[2], r[3]);
+          const uint32_t l01 = b_pack2<ELEM>(r[0] - b_lo16<ELEM>(h01), r[1] - b_hi16<ELEM>(h01));
+          const uint32_t l23 = b_pack2<ELEM>(r[2] - b_lo16<ELEM>(h23), r[3] - b_hi16<ELEM>(h23));
           *reinterpret_cast<uint2*>(zp) = uint2{h01, h23};
           *reinterpret_cast<uint2*>(zp + zhalf) = uint2{l01, l23};
         }
@@ -701,58 +714,124 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
         const int orow = G.orow0 + 16 * B + n;
         const bool rows_in = G.vec_out && G.orow0 + 16 * B + 16 <= G.row_end;  // uniform
         gdst_t rowp = G.dst + ((int64_t)orow * S.out_pitch + G.ocol0 + 4 * g) * (ELEM == kU8 ? 1 : 4);
-        for (int cb0 = cw; cb0 < G.nbh; cb0 += NB * NW) {
-          v4i a[NB][KM], al[NB][ELEM == kU8 ? 1 : KM];
+        if constexpr (ELEM == kU8 && NB == 4) {
+          // Integer outputs by pairs of adjacent column blocks: one swap of
+          // lane-group halves (v_permlane16_swap) leaves each lane 8
+          // consecutive bytes of one row, so one store covers 16 rows x 32
+          // bytes instead of 16 rows x 16 bytes. Wave cw takes pairs cw,
+          // cw + NW, cw + 2 NW, ..., two per iteration.
+          const bool pitch8 = (S.out_pitch & 7) == 0;
+          gdst_t rowq = G.dst + (int64_t)orow * S.out_pitch + G.ocol0 + 16 * (g & 1) + 8 * (g >> 1);
+          for (int p0 = cw; 2 * p0 < G.nbh; p0 += 2 * NW) {
+            v4i a[4][KM];
 #pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            const int cb = min(cb0 + j * NW, G.nbh - 1);
-            const uint8_t* zr = zs + (16 * cb + n) * S.rpitch;
+            for (int j = 0; j < 4; ++j) {
+              const int cb = min(2 * (p0 + (j >> 1) * NW) + (j & 1), G.nbh - 1);
+              const uint8_t* zr = zs + (16 * cb + n) * S.rpitch;
+#pragma unroll
+              for (int k = 0; k < KM; ++k) a[j][k] = *reinterpret_cast<const v4i*>(zr + aoff[k]);
+            }
+            v4i acc[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[j] = v4i{bias, bias, bias, bias};
 #pragma unroll
             for (int k = 0; k < KM; ++k) {
-              a[j][k] = *reinterpret_cast<const v4i*>(zr + aoff[k]);
-              if constexpr (ELEM != kU8) al[j][k] = *reinterpret_cast<const v4i*>(zr + S.zhalf + aoff[k]);
+              if (k > 0 && k >= nk) break;  // uniform
+#pragma unroll
+              for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], bf[k], acc[j], 0, 0, 0);
+            }
+            uint32_t y4[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) y4[j] = b_quant4(acc[j], 0);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              const int cbA = 2 * (p0 + q * NW);  // first block of the pair
+              if (q > 0 && cbA >= G.nbh) break;
+              const auto sw = __builtin_amdgcn_permlane16_swap(y4[2 * q], y4[2 * q + 1], false, false);
+              // uniform: both blocks whole and inside the plane
+              if (rows_in && pitch8 && cbA + 1 < G.nbh && G.ocol0 + 16 * cbA + 32 <= G.col_end) {
+                *(AOL_GLOBAL v2u*)(rowq + 16 * cbA) = v2u{(uint32_t)sw[0], (uint32_t)sw[1]};
+              } else if (orow < G.row_end) {
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj) {
+                  const int cb = cbA + jj;
+                  const int col = G.ocol0 + 16 * cb + 4 * g;
+                  if (cb < G.nbh) {
+                    gdst_t op = rowp + 16 * cb;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                      if (col + i < G.col_end) op[i] = (uint8_t)(y4[2 * q + jj] >> (8 * i));
+                  }
+                }
+              }
             }
           }
-#pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            const int cb = cb0 + j * NW;
-            if (j > 0 && cb >= G.nbh) break;
-            // uniform: the whole 16x16 output block inside the plane
-            const bool inside = rows_in && G.ocol0 + 16 * cb + 16 <= G.col_end;
-            const int col = G.ocol0 + 16 * cb + 4 * g;
-            if constexpr (ELEM == kU8) {
-              v4i acc = {bias, bias, bias, bias}, acch = {0, 0, 0, 0};
-#pragma unroll
+        } else {
+          for (int cb0 = cw; cb0 < G.nbh; cb0 += NB * NW) {
+            v4i a[NB][KM], al[NB][ELEM == kU8 ? 1 : KM];
+  #pragma unroll
+            for (int j = 0; j < NB; ++j) {
+              const int cb = min(cb0 + j * NW, G.nbh - 1);
+              const uint8_t* zr = zs + (16 * cb + n) * S.rpitch;
+  #pragma unroll
               for (int k = 0; k < KM; ++k) {
-                if (k > 0 && k >= nk) break;
-                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], bf[k], acc, 0, 0, 0);
-                if constexpr (split) acch = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], bfh[k], acch, 0, 0, 0);
+                a[j][k] = *reinterpret_cast<const v4i*>(zr + aoff[k]);
+                if constexpr (ELEM != kU8) al[j][k] = *reinterpret_cast<const v4i*>(zr + S.zhalf + aoff[k]);
               }
-              if constexpr (split) acc = acc + acch * 128;
-              const uint32_t y4 = b_quant4(acc, 0);
-              if (inside) {
-                *(AOL_GLOBAL uint32_t*)(rowp + 16 * cb) = y4;
-              } else if (orow < G.row_end) {
-                gdst_t op = rowp + 16 * cb;
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                  if (col + i < G.col_end) op[i] = (uint8_t)(y4 >> (8 * i));
+            }
+            // All the products first, with no branch between them (a block
+            // past the last repeats it; its result is not stored), so the
+            // matrix-core latency of one block hides behind the others.
+            v4i acc[NB], acch[split ? NB : 1];
+            v4f accf[NB];
+  #pragma unroll
+            for (int j = 0; j < NB; ++j) {
+              acc[j] = v4i{bias, bias, bias, bias};
+              if constexpr (split) acch[j] = v4i{0, 0, 0, 0};
+              accf[j] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
+  #pragma unroll
+            for (int k = 0; k < KM; ++k) {
+              if (k > 0 && k >= nk) break;  // uniform
+  #pragma unroll
+              for (int j = 0; j < NB; ++j) {
+                if constexpr (ELEM == kU8) {
+                  acc[j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], bf[k], acc[j], 0, 0, 0);
+                  if constexpr (split) acch[j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[j][k], bfh[k], acch[j], 0, 0, 0);
+                } else {
+                  accf[j] = b_mfma16<ELEM>(a[j][k], bf[k], accf[j]);
+                  accf[j] = b_mfma16<ELEM>(al[j][k], bf[k], accf[j]);
+                }
               }
-            } else {
-              v4f acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-              for (int k = 0; k < KM; ++k) {
-                if (k > 0 && k >= nk) break;
-                acc = b_mfma16<ELEM>(a[j][k], bf[k], acc);
-                acc = b_mfma16<ELEM>(al[j][k], bf[k], acc);
-              }
-              if (inside) {
-                *(AOL_GLOBAL v4f*)(rowp + 64 * cb) = acc;
-              } else if (orow < G.row_end) {
-                AOL_GLOBAL float* op = (AOL_GLOBAL float*)(rowp + 64 * cb);
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                  if (col + i < G.col_end) op[i] = acc[i];
+            }
+  #pragma unroll
+            for (int j = 0; j < NB; ++j) {
+              const int cb = cb0 + j * NW;
+              if (j > 0 && cb >= G.nbh) break;
+              // uniform: the whole 16x16 output block inside the plane
+              const bool inside = rows_in && G.ocol0 + 16 * cb + 16 <= G.col_end;
+              const int col = G.ocol0 + 16 * cb + 4 * g;
+              if constexpr (ELEM == kU8) {
+                v4i r = acc[j];
+                if constexpr (split) r = r + acch[j] * 128;
+                const uint32_t y4 = b_quant4(r, 0);
+                if (inside) {
+                  *(AOL_GLOBAL uint32_t*)(rowp + 16 * cb) = y4;
+                } else if (orow < G.row_end) {
+                  gdst_t op = rowp + 16 * cb;
+  #pragma unroll
+                  for (int i = 0; i < 4; ++i)
+                    if (col + i < G.col_end) op[i] = (uint8_t)(y4 >> (8 * i));
+                }
+              } else {
+                if (inside) {
+                  *(AOL_GLOBAL v4f*)(rowp + 64 * cb) = accf[j];
+                } else if (orow < G.row_end) {
+                  AOL_GLOBAL float* op = (AOL_GLOBAL float*)(rowp + 64 * cb);
+  #pragma unroll
+                  for (int i = 0; i < 4; ++i)
+                    if (col + i < G.col_end) op[i] = accf[j][i];
+                }
               }
             }
           }

@@ -149,14 +149,16 @@ aol_status build_band_stream(const FilterBands& fb, int64_t h, int64_t w, int64_
   return AOL_OK;
 }
 
-BandUnit band_make_unit(const BandStream& S, const FilterBands& fb, int stream, int xb, int sy) {
+int band_max_seg(const AxisBand& vb) { return 16 * std::max(1, 64 / vb.p); }
+
+BandUnit band_make_unit(const BandStream& S, const FilterBands& fb, int stream, int xb, int sy, int seg) {
   const AxisBand& hb = fb.hb;
   const AxisBand& vb = fb.vb;
   BandUnit U;
   memset(&U, 0, sizeof U);
-  const int R0x = xb * S.xreps, R0y = sy * S.seg;
+  const int R0x = xb * S.xreps, R0y = sy * seg;
   const int nRx = std::min(S.xreps, S.rx - R0x);
-  const int nRy = std::min(S.seg, S.ry - R0y);
+  const int nRy = std::min(seg, S.ry - R0y);
   U.stream = stream;
   U.ptr = S.ptr;
   U.Lz = vb.q * (nRy - 1) + vb.span;
@@ -172,13 +174,29 @@ BandUnit band_make_unit(const BandStream& S, const FilterBands& fb, int stream, 
   return U;
 }
 
-int64_t band_unit_cost(const BandStream& S, const AxisBand& vb, int sy) {
-  const int nRy = std::min(S.seg, S.ry - sy * S.seg);
-  const int Lz = vb.q * (nRy - 1) + vb.span;
-  const int64_t steps = (Lz + 15) / 16;
-  // cycles of one workgroup, roughly: per step a fixed part and a part per
-  // staged chunk of the line; per unit its set-up and last vertical blocks
-  return steps * (900 + 12 * (int64_t)S.nch) + 7000;
+int64_t band_unit_cost(const BandStream& S, const BandUnit& U) {
+  // cycles of one workgroup, roughly: per step a fixed part, a part per
+  // staged chunk of the line and one per output block of the two passes;
+  // per unit its set-up and last vertical blocks
+  const int64_t vblocks_per_step = (int64_t)U.nbh * U.NBV / std::max(1, U.M);
+  return (int64_t)U.M * (600 + 8 * (int64_t)S.nch + 25 * (U.nbh + vblocks_per_step)) + 5000;
+}
+
+void band_frame_units(const BandStream* S, const FilterBands* const* fb, const int* seg, int n,
+                      std::vector<BandUnit>& units, std::vector<int64_t>& cost) {
+  units.clear();
+  cost.clear();
+  for (int i = 0; i < n; ++i) {
+    // segments of about equal length (multiples of 16 repetitions, at most seg[i])
+    const int nsy = (S[i].ry + seg[i] - 1) / seg[i];
+    const int sg = 16 * (((S[i].ry + nsy - 1) / nsy + 15) / 16);
+    const int nxb = (S[i].rx + S[i].xreps - 1) / S[i].xreps, ns = (S[i].ry + sg - 1) / sg;
+    for (int sy = 0; sy < ns; ++sy)
+      for (int xb = 0; xb < nxb; ++xb) {
+        units.push_back(band_make_unit(S[i], *fb[i], i, xb, sy, sg));
+        cost.push_back(band_unit_cost(S[i], units.back()));
+      }
+  }
 }
 
 void band_balance(const std::vector<int64_t>& cost, int grid, std::vector<int32_t>& order,

@@ -39,12 +39,21 @@ aol_status build_band_stream(const FilterBands& fb, int64_t h, int64_t w, int64_
 // for the widest) and returns the LDS bytes a workgroup needs for any of them.
 int band_share_staging(BandStream* const* streams, const FilterBands* const* fbs, int n);
 
-// The unit of column band xb and segment sy of stream `stream` (S built by
-// build_band_stream).
-BandUnit band_make_unit(const BandStream& S, const FilterBands& fb, int stream, int xb, int sy);
+// The unit of column band xb and segment sy (of seg repetitions, a multiple
+// of 16) of stream `stream` (S built by build_band_stream).
+BandUnit band_make_unit(const BandStream& S, const FilterBands& fb, int stream, int xb, int sy, int seg);
 
-// Estimated cost of the unit of segment sy of a stream (arbitrary units).
-int64_t band_unit_cost(const BandStream& S, const AxisBand& vb, int sy);
+// Estimated cost of a unit (arbitrary units: about cycles of a workgroup).
+int64_t band_unit_cost(const BandStream& S, const BandUnit& U);
+
+// Longest segment (repetitions, a multiple of 16) of a stream: one lane per
+// vertical output block of a unit.
+int band_max_seg(const AxisBand& vb);
+
+// The units of one frame of n streams, each cut into segments of seg[i]
+// repetitions, with their costs.
+void band_frame_units(const BandStream* S, const FilterBands* const* fb, const int* seg, int n,
+                      std::vector<BandUnit>& units, std::vector<int64_t>& cost);
 
 // Assigns units of the given costs to `grid` workgroups, longest first, each
 // to the least loaded workgroup so far. order: the unit ids grouped by

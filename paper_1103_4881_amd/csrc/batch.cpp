@@ -86,19 +86,6 @@ static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
     budget -= std::max(lds - sc.budget, 1024);
     if (budget < 8 * 1024) return fail(AOL_ERR_UNSUPPORTED, "batch streams do not fit %d bytes of LDS", sc.budget);
   }
-  // units in stream order (so a workgroup's units mostly share a filter),
-  // assigned to workgroups by their estimated cost
-  std::vector<BandUnit> units;
-  std::vector<int64_t> cost;
-  for (int i = 0; i < bp->n; ++i) {
-    const BandStream& S = streams[i];
-    const int nxb = (S.rx + S.xreps - 1) / S.xreps, nsy = (S.ry + S.seg - 1) / S.seg;
-    for (int sy = 0; sy < nsy; ++sy)
-      for (int xb = 0; xb < nxb; ++xb) {
-        units.push_back(band_make_unit(S, bp->bands[bp->filt[i]], i, xb, sy));
-        cost.push_back(band_unit_cost(S, bp->bands[bp->filt[i]].vb, sy));
-      }
-  }
   int wg = 0;
   hipError_t e = band_prepare(bp->elem, slots, bp->split, bp->kmax, (size_t)lds, &wg);
   if (e != hipSuccess) return hip_fail(e, "band kernel attributes");
@@ -107,6 +94,36 @@ static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
   if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return hip_fail(e, "hipDeviceGetAttribute");
+  // Units in stream order (so a workgroup's units mostly share a filter),
+  // assigned to workgroups by their estimated cost. Segments of the
+  // schedule's length (0: about 512 input lines); a stream whose units would
+  // each cost more than a workgroup's fair share gets shorter ones.
+  std::vector<const FilterBands*> fbs(bp->n);
+  std::vector<int> segs(bp->n);
+  for (int i = 0; i < bp->n; ++i) {
+    fbs[i] = &bp->bands[bp->filt[i]];
+    const int q = fbs[i]->vb.q;
+    const int want = sc.seg > 0 ? sc.seg : 16 * ((512 + 16 * q - 1) / (16 * q));
+    segs[i] = std::max(16, std::min(want, band_max_seg(fbs[i]->vb)));
+  }
+  std::vector<BandUnit> units;
+  std::vector<int64_t> cost;
+  for (int round = 0; round < 8; ++round) {
+    band_frame_units(streams.data(), fbs.data(), segs.data(), bp->n, units, cost);
+    int64_t total = 0;
+    for (int64_t c : cost) total += c;
+    const int64_t share = total / std::max<int64_t>(1, std::min<int64_t>((int64_t)wg * cus, (int64_t)units.size()));
+    bool cut = false;
+    for (size_t k = 0; k < units.size(); ++k) {
+      const int i = units[k].stream;
+      if (cost[k] > share && segs[i] > 16) {
+        segs[i] = std::max(16, segs[i] / 2 / 16 * 16);
+        cut = true;
+        while (k + 1 < units.size() && units[k + 1].stream == i) ++k;
+      }
+    }
+    if (!cut) break;
+  }
   // the descriptor buffers keep their addresses across schedules (allocated
   // once at full capacity), so a graph captured earlier never reads freed memory
   if (units.size() > bp->unit_capacity) return fail(AOL_ERR_INVALID, "unit capacity exceeded");
@@ -132,7 +149,7 @@ static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
   bp->sched = sc;
   char buf[160];
   snprintf(buf, sizeof buf, "{\"seg\": %d, \"lds_budget\": %d, \"units\": %d, \"grid\": %d, \"lds\": %d}",
-           bp->streams.empty() ? 0 : bp->streams[0].seg, sc.budget, (int)bp->units.size(), bp->grid, lds);
+           sc.seg, sc.budget, (int)bp->units.size(), bp->grid, lds);
   bp->sched_json = buf;
   return AOL_OK;
 }

@@ -264,18 +264,20 @@ struct aol_plan {
   int walk = 0;  // 0: row-major tiles inside a plane, 1: column-major
   // band schedule: full-width (or column-band) segments streamed down each plane
   bool use_band = false;
-  int bslots = 0, bgrid = 0, bunits = 0;
+  int bslots = 0, bgrid = 0;
+  int bseg = 0;  // requested segment (repetitions), 0: chosen per launch
   size_t blds = 0;
   FilterBands fbands;
   BandStream bstreams[kMaxPlanes];
-  DeviceBuf d_bstreams, d_bunits;
-  std::vector<int64_t> bcost;  // estimated cost of each unit of one frame
-  // Balanced unit order per frame count launched so far. Kept until the plan
-  // is destroyed: a graph that captured a launch copies from the host arrays.
+  DeviceBuf d_bstreams;
+  // Units (of one frame) and their balanced order, per frame count launched
+  // so far. Kept until the plan is destroyed: a graph that captured a launch
+  // copies from the host arrays.
   struct BandSched {
     int frames = 0;
+    std::vector<BandUnit> units;
     std::vector<int32_t> order, first;
-    DeviceBuf d_order, d_first;
+    DeviceBuf d_units, d_order, d_first;
   };
   std::vector<std::unique_ptr<BandSched>> bsched;
   bool split = false;
@@ -393,8 +395,6 @@ static aol_status plan_build_band(aol_plan* pl, int xreps, int seg) {
   aol_status st = build_filter_bands(pl->hf, pl->vf, pl->elem, false, fb);
   if (st) return st == AOL_ERR_UNSUPPORTED ? AOL_OK : st;
   int lds = 0, slots = 0;
-  std::vector<BandUnit> units;
-  std::vector<int64_t> costs;
   for (int i = 0; i < pl->n_planes; ++i) {
     int l = 0, sl = 0;
     st = build_band_stream(fb, pl->planes[i].height, pl->planes[i].width, pl->planes[i].in_pitch,
@@ -403,13 +403,6 @@ static aol_status plan_build_band(aol_plan* pl, int xreps, int seg) {
     pl->bstreams[i].ptr = i;
     lds = std::max(lds, l);
     slots = std::max(slots, sl);
-    const BandStream& S = pl->bstreams[i];
-    const int nxb = (S.rx + S.xreps - 1) / S.xreps, nsy = (S.ry + S.seg - 1) / S.seg;
-    for (int sy = 0; sy < nsy; ++sy)
-      for (int xb = 0; xb < nxb; ++xb) {
-        units.push_back(band_make_unit(S, fb, i, xb, sy));
-        costs.push_back(band_unit_cost(S, fb.vb, sy));
-      }
   }
   {
     std::vector<BandStream*> sp;
@@ -429,19 +422,58 @@ static aol_status plan_build_band(aol_plan* pl, int xreps, int seg) {
   if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return hip_fail(e, "hipDeviceGetAttribute");
-  DeviceBuf ds, du;
+  DeviceBuf ds;
   if ((st = ds.upload(pl->bstreams, sizeof(BandStream) * pl->n_planes))) return st;
-  if ((st = du.upload(units.data(), sizeof(BandUnit) * units.size()))) return st;
   pl->fbands = std::move(fb);  // moves ownership; the device addresses in the streams stay valid
   pl->d_bstreams = std::move(ds);
-  pl->d_bunits = std::move(du);
-  pl->bunits = (int)units.size();
-  pl->bcost = std::move(costs);
+  pl->bseg = seg;
   pl->bsched.clear();
   pl->bslots = slots;
   pl->blds = (size_t)lds;
   pl->bgrid = wg * cus;
   pl->use_band = true;
+  return AOL_OK;
+}
+
+// Segment length of each plane for a launch of n_frames frames: the
+// requested one, else the longest of about 1024, 512, ... 64 input lines that
+// still gives every resident workgroup a few units to balance.
+static aol_status band_plan_schedule(aol_plan* plan, int n_frames, hipStream_t stream) {
+  const FilterBands* fbs[kMaxPlanes];
+  for (int i = 0; i < plan->n_planes; ++i) fbs[i] = &plan->fbands;
+  const AxisBand& vb = plan->fbands.vb;
+  auto ns = std::make_unique<aol_plan::BandSched>();
+  ns->frames = n_frames;
+  std::vector<int64_t> frame_cost;
+  for (int lines = 1024;; lines /= 2) {
+    int seg = plan->bseg > 0 ? plan->bseg : 16 * ((lines + 16 * vb.q - 1) / (16 * vb.q));
+    seg = std::max(16, std::min(seg, band_max_seg(vb)));
+    int segs[kMaxPlanes];
+    for (int i = 0; i < plan->n_planes; ++i) segs[i] = seg;
+    band_frame_units(plan->bstreams, fbs, segs, plan->n_planes, ns->units, frame_cost);
+    if (plan->bseg > 0 || lines <= 64 || (int64_t)ns->units.size() * n_frames >= 4 * (int64_t)plan->bgrid) break;
+  }
+  const int64_t total = (int64_t)ns->units.size() * n_frames;
+  if (total > INT_MAX) return fail(AOL_ERR_UNSUPPORTED, "too many units in one launch");
+  std::vector<int64_t> cost((size_t)total);
+  for (int f = 0; f < n_frames; ++f)
+    std::copy(frame_cost.begin(), frame_cost.end(), cost.begin() + (size_t)f * ns->units.size());
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, plan->bgrid));
+  band_balance(cost, grid, ns->order, ns->first);
+  aol_status st = ns->d_units.alloc(sizeof(BandUnit) * ns->units.size());
+  if (!st) st = ns->d_order.alloc(sizeof(int32_t) * ns->order.size());
+  if (!st) st = ns->d_first.alloc(sizeof(int32_t) * ns->first.size());
+  if (st) return st;
+  hipError_t e = hipMemcpyAsync(ns->d_units.ptr, ns->units.data(), sizeof(BandUnit) * ns->units.size(),
+                                hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ns->d_order.ptr, ns->order.data(), sizeof(int32_t) * ns->order.size(),
+                       hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ns->d_first.ptr, ns->first.data(), sizeof(int32_t) * ns->first.size(),
+                       hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "unit schedule upload");
+  plan->bsched.push_back(std::move(ns));
   return AOL_OK;
 }
 
@@ -617,11 +649,7 @@ static aol_status run_fused(aol_plan* plan, int32_t n_frames, const void* const*
     BandLaunch L;
     memset(&L, 0, sizeof L);
     L.streams = (const BandStream*)plan->d_bstreams.ptr;
-    L.units = (const BandUnit*)plan->d_bunits.ptr;
-    L.units_per_frame = plan->bunits;
     L.n_frames = n_frames;
-    if ((int64_t)plan->bunits * n_frames > INT_MAX) return fail(AOL_ERR_UNSUPPORTED, "too many units in one launch");
-    L.total_units = plan->bunits * n_frames;
     bool aligned = true;
     const int ein = 16 / in_es;
     for (int i = 0; i < plan->n_planes; ++i) {
@@ -635,33 +663,22 @@ static aol_status run_fused(aol_plan* plan, int32_t n_frames, const void* const*
     L.aligned = aligned ? 1 : 0;
     bool gather = !aligned;
     for (int i = 0; i < plan->n_planes; ++i) gather = gather || !plan->bstreams[i].vec_in;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(L.total_units, plan->bgrid));
-    // the balanced unit order for this frame count (built and copied to the
-    // device on the stream at the first launch with it)
+    // The units and their balanced order for this frame count, built and
+    // copied to the device on the stream at the first launch with it.
     aol_plan::BandSched* sc = nullptr;
     for (auto& x : plan->bsched)
       if (x->frames == n_frames) sc = x.get();
     if (!sc) {
-      auto ns = std::make_unique<aol_plan::BandSched>();
-      ns->frames = n_frames;
-      std::vector<int64_t> cost((size_t)L.total_units);
-      for (int f = 0; f < n_frames; ++f)
-        std::copy(plan->bcost.begin(), plan->bcost.end(), cost.begin() + (size_t)f * plan->bunits);
-      band_balance(cost, grid, ns->order, ns->first);
-      aol_status st = ns->d_order.alloc(sizeof(int32_t) * ns->order.size());
-      if (!st) st = ns->d_first.alloc(sizeof(int32_t) * ns->first.size());
+      aol_status st = band_plan_schedule(plan, n_frames, stream);
       if (st) return st;
-      hipError_t e = hipMemcpyAsync(ns->d_order.ptr, ns->order.data(), sizeof(int32_t) * ns->order.size(),
-                                    hipMemcpyHostToDevice, stream);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(ns->d_first.ptr, ns->first.data(), sizeof(int32_t) * ns->first.size(),
-                           hipMemcpyHostToDevice, stream);
-      if (e != hipSuccess) return hip_fail(e, "unit order upload");
-      sc = ns.get();
-      plan->bsched.push_back(std::move(ns));
+      sc = plan->bsched.back().get();
     }
+    L.units = (const BandUnit*)sc->d_units.ptr;
+    L.units_per_frame = (int32_t)sc->units.size();
+    L.total_units = L.units_per_frame * n_frames;
     L.order = (const int32_t*)sc->d_order.ptr;
     L.first = (const int32_t*)sc->d_first.ptr;
+    const int grid = (int)sc->first.size() - 1;
     hipError_t e = band_launch(plan->elem, plan->bslots, plan->fbands.split, plan->fbands.kmax, gather, L, grid,
                                plan->blds, stream);
     if (e != hipSuccess) return hip_fail(e, "band kernel launch");

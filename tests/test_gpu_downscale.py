@@ -111,6 +111,17 @@ def test_unaligned_pitches_and_guard_bytes():
     np.testing.assert_array_equal(Y, pp.downscale_u8(X, of, ov))
 
 
+@pytest.mark.parametrize("w,out_pad", [(512, 0), (512, 4), (512, 8), (400, 4), (464, 0)])
+def test_output_pitches_paired_stores(w, out_pad):
+    # output rows of 192 / 150 / 174 bytes with pitches that are and are not
+    # multiples of 8, odd and even counts of 16-column output blocks
+    hf, of = _filters(3, 8, 11)
+    vf, ov = _filters(3, 8, 11)
+    X = synthgen.uniform_frame(8, 96, w, idx=2)[None]
+    (Y,) = _run_u8([X], hf, vf, out_pitch_pad=out_pad)
+    np.testing.assert_array_equal(Y, pp.downscale_u8(X, of, ov))
+
+
 def test_i420_frames_every_tile_shape_identical():
     """Three planes, several frames, every tile shape: identical bytes (independent elementary tasks)."""
     Yp, Up, Vp = synthgen.yuv420_frames(7, 3, 360, 640)
