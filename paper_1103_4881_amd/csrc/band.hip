@@ -62,6 +62,15 @@ __device__ __forceinline__ void lds_barrier() {
 
 
 constexpr int kBandWaves = kBandThreads / 64;
+constexpr int kBandLoadWaves = kBandLoadThreads / 64;
+static_assert(kBandMinHShares == kBandWaves, "every wave takes at least one share of the horizontal pass");
+
+// Shares of the horizontal pass each loading wave takes: two where the
+// registers allow (the compute waves also run the vertical pass), else one.
+template <bool SPLIT, int KM, int SLOTS>
+struct BandLoadShares {
+  static constexpr int value = SPLIT || (KM >= 2 && SLOTS >= 4) ? 1 : 2;
+};
 
 // Pointers read from memory (descriptor and pointer tables) are generic to
 // the compiler, and generic accesses become flat instructions, which count
@@ -275,14 +284,16 @@ struct BandFeed {
   }
 };
 
-// Horizontal pass of one step by one wave. Every wave of the workgroup
-// takes part, and each takes blocks of one position lb within the period
-// (waves w = lb, lb + nblk, ...: wave w handles blocks lb + nblk*(w/nblk +
-// gw*i), gw the waves sharing lb), so its coefficient operands and biases
-// are the same for all its blocks and stay in registers for the whole unit,
-// and its blocks' staged chunks and ring rows advance by fixed strides.
-// Writes 16 intermediate lines of each of its 16-column blocks, transposed,
-// into the ring.
+// Horizontal pass of one step by one share. The pass is cut into shares:
+// one or two for each loading wave and one for each compute wave (the
+// compute waves also run the vertical pass). Each share takes
+// blocks of one position lb within the period (shares v = lb, lb + nblk,
+// ...: share v handles blocks lb + nblk*(v/nblk + gw*i), gw the shares of
+// position lb), so its coefficient operands and biases are the same for all
+// its blocks and stay in registers for the whole unit, and its blocks'
+// staged chunks and ring rows advance by fixed strides. Writes 16
+// intermediate lines of each of its 16-column blocks, transposed, into the
+// ring.
 template <int ELEM, bool SPLIT, int KM, int NB>  // NB: blocks per iteration (operands in flight)
 struct BandH {
   static constexpr int ES = ELEM == kU8 ? 1 : 2;
@@ -298,13 +309,14 @@ struct BandH {
   const uint8_t* xa;  // lane's A chunk of the wave's first block (staging buffer 0)
   uint8_t* zl;        // lane's ring row of the wave's first block
 
-  __device__ __forceinline__ void setup(const BandStream& S, const BandUnitGeo& G, const uint8_t* lds, int w,
+  // v: this share's index among the nv shares of the pass
+  __device__ __forceinline__ void setup(const BandStream& S, const BandUnitGeo& G, const uint8_t* lds, int v, int nv,
                                         int lane) {
     const cband_t hb = (cband_t)S.hb;
     const int g = lane >> 4, n = lane & 15;
     const int nblk = hb->nblk;
-    const int lb = w % nblk, r = w / nblk;
-    const int gw = (kBandWaves - lb + nblk - 1) / nblk;  // waves with this position
+    const int lb = v % nblk, r = v / nblk;
+    const int gw = (nv - lb + nblk - 1) / nblk;  // shares with this position
     const int b0 = lb + nblk * r, bstep = nblk * gw;
     nbi = b0 < G.nbh ? (G.nbh - b0 + bstep - 1) / bstep : 0;
     nk = hb->nk[lb];
@@ -510,8 +522,9 @@ struct BandCursor {
 // flight at the loop head are the same sets in the same order on entry and
 // on the back edge, and their waits count exactly (on gfx9 a wave with loads
 // and stores outstanding can only wait for all of them).
-template <int ELEM, int SLOTS, class HP>
+template <int ELEM, int SLOTS, int LS, class HP>
 __device__ __forceinline__ void band_load_pipeline(const BandLaunch& L, uint8_t* lds, int tid, int wave, int lane) {
+  constexpr int NV = LS * kBandLoadWaves + (kBandWaves - kBandLoadWaves);  // shares of the horizontal pass
   constexpr int D = BandDepth<SLOTS>::value;
   const int g = lane >> 4;
   int i, i1;  // position in the unit order, end of the workgroup's share
@@ -524,8 +537,9 @@ __device__ __forceinline__ void band_load_pipeline(const BandLaunch& L, uint8_t*
   C.at(S, G, i, tid);
   int xo[SLOTS];
   BandFeed<ELEM, SLOTS>::offsets(S, tid, xo);
-  HP H;
-  H.setup(S, G, lds, wave, lane);
+  HP H, H2;  // this wave's shares of the horizontal pass (H2: when LS is 2)
+  H.setup(S, G, lds, wave, NV, lane);
+  if constexpr (LS == 2) H2.setup(S, G, lds, wave + kBandLoadWaves, NV, lane);
   v4i pre[D][SLOTS];
 #pragma unroll
   for (int k = 0; k < D; ++k) {
@@ -537,6 +551,7 @@ __device__ __forceinline__ void band_load_pipeline(const BandLaunch& L, uint8_t*
   C.advance(L, tid);
   lds_barrier();  // step 0 staged, the unit's coefficients in place
   H.load_operands();
+  if constexpr (LS == 2) H2.load_operands();
   int m = 0, t = 0, zm = 0;  // step within the unit, step within the workgroup, ring line
   bool live = true;          // uniform: units left
   // Whole groups of D steps (the register set of a step is a constant once
@@ -555,7 +570,8 @@ __device__ __forceinline__ void band_load_pipeline(const BandLaunch& L, uint8_t*
       C.issue(pre[j]);
       C.advance(L, tid);
       if (live) {
-        H.run(zm, t & 1, g);  // this wave's share of step m's horizontal pass
+        H.run(zm, t & 1, g);  // this wave's shares of step m's horizontal pass
+        if constexpr (LS == 2) H2.run(zm, t & 1, g);
         zm = zm + 16 == S.ring ? 0 : zm + 16;
         lds_barrier();  // step m done with its buffer, the next step staged
         if (last) {
@@ -564,11 +580,13 @@ __device__ __forceinline__ void band_load_pipeline(const BandLaunch& L, uint8_t*
           live = i < i1;
           if (live) {
             band_unit<ELEM>(L, band_unit_at(L, i), S, G);
-            H.setup(S, G, lds, wave, lane);
+            H.setup(S, G, lds, wave, NV, lane);
+            if constexpr (LS == 2) H2.setup(S, G, lds, wave + kBandLoadWaves, NV, lane);
             m = -1;
             zm = 0;
             lds_barrier();  // the unit's coefficients in place (its step 0 was staged before)
             H.load_operands();
+            if constexpr (LS == 2) H2.load_operands();
           }
         }
       }
@@ -582,8 +600,9 @@ __device__ __forceinline__ void band_load_pipeline(const BandLaunch& L, uint8_t*
 
 // Loading waves for lines that are gathered element by element: no
 // prefetch, unit by unit (a call, which waits for every load it issues).
-template <int ELEM, int SLOTS, class HP>
+template <int ELEM, int SLOTS, int LS, class HP>
 __device__ __forceinline__ void band_load_gathered(const BandLaunch& L, uint8_t* lds, int tid, int wave, int lane) {
+  constexpr int NV = LS * kBandLoadWaves + (kBandWaves - kBandLoadWaves);
   const int g = lane >> 4;
   int t0 = 0;  // the unit's first step within the workgroup (staging buffer parity)
   int i0, i1;
@@ -594,16 +613,19 @@ __device__ __forceinline__ void band_load_gathered(const BandLaunch& L, uint8_t*
     band_unit<ELEM>(L, band_unit_at(L, i), S, G);
     BandFeed<ELEM, SLOTS> F;
     F.setup(S, G, tid);
-    HP H;
-    H.setup(S, G, lds, wave, lane);
+    HP H, H2;
+    H.setup(S, G, lds, wave, NV, lane);
+    if constexpr (LS == 2) H2.setup(S, G, lds, wave + kBandLoadWaves, NV, lane);
     uint8_t* xs = lds + S.lds_x;
     F.stage_gathered(S, G, 0, xs + (t0 & 1) * S.xbuf);
     lds_barrier();  // step 0 staged, the unit's coefficients in place
     H.load_operands();
+    if constexpr (LS == 2) H2.load_operands();
     int zm = 0;
     for (int m = 0; m < G.M; ++m) {
       if (m + 1 < G.M) F.stage_gathered(S, G, m + 1, xs + ((t0 + m + 1) & 1) * S.xbuf);
       H.run(zm, (t0 + m) & 1, g);
+      if constexpr (LS == 2) H2.run(zm, (t0 + m) & 1, g);
       zm = zm + 16 == S.ring ? 0 : zm + 16;
       lds_barrier();  // step m done with its buffer, step m+1 staged
     }
@@ -622,6 +644,8 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
   constexpr bool split = (ELEM == kU8) && SPLIT;
   constexpr int NW = (kBandThreads - kBandLoadThreads) / 64;  // compute waves
   constexpr int NB = KM <= 2 && !split ? 4 : 1;               // blocks per iteration (operands in flight)
+  constexpr int LS = BandLoadShares<split, KM, SLOTS>::value;  // horizontal shares per loading wave
+  constexpr int NV = LS * kBandLoadWaves + NW;                 // shares of the horizontal pass
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -637,8 +661,8 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
   if (loader) {
     if (i0 >= i1) return;
     // one block at a time in the horizontal pass: the prefetch holds the registers
-    if constexpr (GATHER) band_load_gathered<ELEM, SLOTS, BandH<ELEM, split, KM, 1>>(L, lds, tid, wave, lane);
-    else band_load_pipeline<ELEM, SLOTS, BandH<ELEM, split, KM, 1>>(L, lds, tid, wave, lane);
+    if constexpr (GATHER) band_load_gathered<ELEM, SLOTS, LS, BandH<ELEM, split, KM, 1>>(L, lds, tid, wave, lane);
+    else band_load_pipeline<ELEM, SLOTS, LS, BandH<ELEM, split, KM, 1>>(L, lds, tid, wave, lane);
     return;
   }
 
@@ -681,7 +705,7 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
     // this wave's share of the horizontal pass, and the unit's vertical
     // blocks (lane B: block B)
     BandH<ELEM, split, KM, NB> H;
-    H.setup(S, G, lds, wave, lane);
+    H.setup(S, G, lds, (LS - 1) * kBandLoadWaves + wave, NV, lane);  // the last shares
     uint32_t vtbl = 0;  // lane B: vertical block B (read after the unit's first barrier)
     int vneed = 0;      // and the intermediate lines its window reaches
     const int vz = vb->zfrag;

@@ -15,6 +15,9 @@ aol_status build_filter_bands(const FilterHost& hf, const FilterHost& vf, int el
   AxisBand hb, vb;
   aol_status st = build_band(hf, 16, elem, true, force_split, hb, hfr, "hf");
   if (st) return st;
+  if (hb.nblk > kBandMinHShares)
+    return fail(AOL_ERR_UNSUPPORTED, "hf: %d output blocks per period exceed the band kernel's %d", hb.nblk,
+                kBandMinHShares);
   st = build_band(vf, 16, elem, false, force_split || hb.split != 0, vb, vfr, "vf");
   if (st) return st;
   if (vb.split && !hb.split) {  // one kernel instance carries both axes: same operand layout
