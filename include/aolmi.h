@@ -146,7 +146,7 @@ aol_status aol_plan_set_tile(aol_plan* plan, int32_t tile_rx, int32_t tile_ry);
  * unit, normally the full width) and streams segments of seg_reps
  * repetitions down the plane, keeping the intermediate in an LDS ring.
  * seg_reps 0: chosen at the first launch with a given frame count (the
- * longest of about 1024 ... 64 input lines that leaves every workgroup a few
+ * longest of about 512 ... 64 input lines that leaves every workgroup a few
  * units; that launch copies the schedule to the device on its stream).
  * Multiples of 16. Selecting a band re-selects the band kernel after
  * aol_plan_set_tile. AOL_ERR_UNSUPPORTED if the band does not fit. Results

@@ -439,7 +439,14 @@ class BatchPlan:
         self._graphs = []
 
     def set_pointers(self, ins, outs, stream=None):
+        self.set_pointer_arrays(self.pointer_arrays(ins, outs), stream)
+
+    def pointer_arrays(self, ins, outs):
+        """Checks one frame's tensors and returns their device addresses as the two
+        pointer arrays `set_pointer_arrays` takes (build them once per set of buffers)."""
         import torch
+        if len(ins) != len(self.shapes) or len(outs) != len(self.shapes):
+            raise ValueError("one input and one output per stream")
         for t, (h, w), o, (oh, ow) in zip(ins, self.shapes, outs, self.out_shapes):
             if not (t.is_cuda and o.is_cuda) or t.shape[-2:] != (h, w) or o.shape[-2:] != (oh, ow):
                 raise ValueError("one [h, w] input and one [out_h, out_w] output device tensor per stream")
@@ -449,7 +456,12 @@ class BatchPlan:
                 raise ValueError("u8 batches take uint8 tensors")
             if self.precision != "u8" and (t.element_size() != 2 or o.dtype != torch.float32):
                 raise ValueError("float batches take 16-bit inputs and float32 outputs")
-        aol_batch_set_pointers(self._h, [t.data_ptr() for t in ins], [o.data_ptr() for o in outs], stream)
+        return _ptrs([t.data_ptr() for t in ins]), _ptrs([o.data_ptr() for o in outs])
+
+    def set_pointer_arrays(self, arrays, stream=None):
+        """Points the next launches at the buffers of `pointer_arrays` (a stream-ordered
+        update of the device pointer table; the tensors must stay alive)."""
+        _check(_lib.aol_batch_set_pointers(self._h, arrays[0], arrays[1], _stream_handle(stream)))
 
     def run(self, stream=None):
         aol_batch_run(self._h, stream)

@@ -643,7 +643,10 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
   constexpr int E = 16 / ES;
   constexpr bool split = (ELEM == kU8) && SPLIT;
   constexpr int NW = (kBandThreads - kBandLoadThreads) / 64;  // compute waves
-  constexpr int NB = KM <= 2 && !split ? 4 : 1;               // blocks per iteration (operands in flight)
+  constexpr int NB = KM <= 2 && !split ? 4 : 1;               // vertical blocks per iteration (operands in flight)
+  // horizontal blocks per iteration: about two per share and step at the usual ratios
+  constexpr int NBH = NB > 2 ? 2 : NB;
+  constexpr int NBL = KM == 1 && !split && SLOTS <= 4 ? 2 : 1;  // the same for the loading waves
   constexpr int LS = BandLoadShares<split, KM, SLOTS>::value;  // horizontal shares per loading wave
   constexpr int NV = LS * kBandLoadWaves + NW;                 // shares of the horizontal pass
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
@@ -660,9 +663,9 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
   band_share(L, i0, i1);
   if (loader) {
     if (i0 >= i1) return;
-    // one block at a time in the horizontal pass: the prefetch holds the registers
+    // few blocks at a time in the horizontal pass: the prefetch holds the registers
     if constexpr (GATHER) band_load_gathered<ELEM, SLOTS, LS, BandH<ELEM, split, KM, 1>>(L, lds, tid, wave, lane);
-    else band_load_pipeline<ELEM, SLOTS, LS, BandH<ELEM, split, KM, 1>>(L, lds, tid, wave, lane);
+    else band_load_pipeline<ELEM, SLOTS, LS, BandH<ELEM, split, KM, NBL>>(L, lds, tid, wave, lane);
     return;
   }
 
@@ -704,7 +707,7 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
     }
     // this wave's share of the horizontal pass, and the unit's vertical
     // blocks (lane B: block B)
-    BandH<ELEM, split, KM, NB> H;
+    BandH<ELEM, split, KM, NBH> H;
     H.setup(S, G, lds, (LS - 1) * kBandLoadWaves + wave, NV, lane);  // the last shares
     uint32_t vtbl = 0;  // lane B: vertical block B (read after the unit's first barrier)
     int vneed = 0;      // and the intermediate lines its window reaches

@@ -436,7 +436,7 @@ static aol_status plan_build_band(aol_plan* pl, int xreps, int seg) {
 }
 
 // Segment length of each plane for a launch of n_frames frames: the
-// requested one, else the longest of about 1024, 512, ... 64 input lines that
+// requested one, else the longest of about 512, 256, 128, 64 input lines that
 // still gives every resident workgroup a few units to balance.
 static aol_status band_plan_schedule(aol_plan* plan, int n_frames, hipStream_t stream) {
   const FilterBands* fbs[kMaxPlanes];
@@ -445,7 +445,7 @@ static aol_status band_plan_schedule(aol_plan* plan, int n_frames, hipStream_t s
   auto ns = std::make_unique<aol_plan::BandSched>();
   ns->frames = n_frames;
   std::vector<int64_t> frame_cost;
-  for (int lines = 1024;; lines /= 2) {
+  for (int lines = 512;; lines /= 2) {
     int seg = plan->bseg > 0 ? plan->bseg : 16 * ((lines + 16 * vb.q - 1) / (16 * vb.q));
     seg = std::max(16, std::min(seg, band_max_seg(vb)));
     int segs[kMaxPlanes];

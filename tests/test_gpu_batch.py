@@ -59,8 +59,11 @@ def test_batch_u8_run_and_graph_bit_exact():
         plan.set_pointers([ins[i][0] for i in range(len(st))], [outs[i][0] for i in range(len(st))], s)
         plan.run(s)
         g = plan.graph(s)
-        for k in range(1, steps):
-            plan.set_pointers([ins[i][k] for i in range(len(st))], [outs[i][k] for i in range(len(st))], s)
+        # pointer arrays built once, as a serving loop keeps them; step 2 uses them twice
+        tables = [plan.pointer_arrays([ins[i][k] for i in range(len(st))], [outs[i][k] for i in range(len(st))])
+                  for k in range(steps)]
+        for k in list(range(1, steps)) + [steps - 1]:
+            plan.set_pointer_arrays(tables[k], s)
             aol.aol_graph_launch(g, s)
     s.synchronize()
     for i, (h, w, hf, vf, of, ov) in enumerate(st):
