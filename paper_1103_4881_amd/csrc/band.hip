@@ -318,17 +318,21 @@ struct BandH {
     const int lb = v % nblk, r = v / nblk;
     const int gw = (nv - lb + nblk - 1) / nblk;  // shares with this position
     const int b0 = lb + nblk * r, bstep = nblk * gw;
-    nbi = b0 < G.nbh ? (G.nbh - b0 + bstep - 1) / bstep : 0;
-    nk = hb->nk[lb];
+    // Wave-uniform by construction, and said so: values the compiler keeps
+    // in vector registers make the block loop divergent, and a K-step skipped
+    // under an EXEC mask is not skipped at all (MFMA ignores EXEC), so the
+    // stale operands of an unused K-step would be added in.
+    nbi = __builtin_amdgcn_readfirstlane(b0 < G.nbh ? (G.nbh - b0 + bstep - 1) / bstep : 0);
+    nk = __builtin_amdgcn_readfirstlane(hb->nk[lb]);
     const int fb = hb->frag[lb];
     fl = lds + S.lds_fh + lane * 16 + fb * (SPLIT ? 2048 : 1024);
     bl = lds + S.lds_bh + (lb * 16 + n) * 4;
     const int per0 = b0 / nblk;          // period of the first block
     const int pchunks = hb->q * 16 / E;  // chunks per period (16q elements)
     xa = lds + S.lds_x + n * S.xpitch + (hb->chunk0[lb] + per0 * pchunks + g) * 16;
-    astep = gw * pchunks * 16;
+    astep = __builtin_amdgcn_readfirstlane(gw * pchunks * 16);
     zl = const_cast<uint8_t*>(lds) + S.lds_z + (16 * b0 + n) * S.rpitch;
-    zstep = 16 * bstep * S.rpitch;
+    zstep = __builtin_amdgcn_readfirstlane(16 * bstep * S.rpitch);
     xbuf = S.xbuf;
     zhalf = S.zhalf;
   }

@@ -39,17 +39,25 @@ struct aol_batch_plan {
   std::vector<FilterHost> hf, vf;
   std::vector<int> filt;              // filter group of each stream
   std::vector<FilterBands> bands;     // one per filter group
-  bool split = false;
-  int kmax = 0;  // largest K-step count over the filter groups
+  // The streams whose filters fit int8 taps and those that need the split
+  // operands run as two launches (each with its own kernel instance), so
+  // one filter with large taps does not slow down the others.
+  struct Part {
+    bool split = false;
+    int kmax = 0;                     // largest K-step count over the part's filter groups
+    std::vector<int> ids;             // its streams
+    size_t unit_capacity = 0;
+    // built for the current schedule
+    std::vector<BandUnit> units;
+    int slots = 0, grid = 0;
+    size_t lds = 0;
+    bool gather = false;
+    DeviceBuf d_units, d_order, d_first;  // unit_capacity, unit_capacity, unit_capacity + 1 entries
+  };
+  Part parts[2];
   Schedule sched;
-  // built for the current schedule
   std::vector<BandStream> streams;
-  std::vector<BandUnit> units;
-  int slots = 0, grid = 0;
-  size_t lds = 0;
-  size_t unit_capacity = 0;
-  DeviceBuf d_streams, d_units, d_table;
-  DeviceBuf d_order, d_first;  // balanced unit order: unit_capacity and unit_capacity + 1 entries
+  DeviceBuf d_streams, d_table;
   bool pointers_set = false;
   std::string cache_path, key, sched_json;
 };
@@ -59,35 +67,38 @@ struct aol_graph {
   hipGraphExec_t exec = nullptr;
 };
 
-static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
-  std::vector<BandStream> streams(bp->n);
+// One part's streams, units and balanced order for a schedule.
+static aol_status batch_build_part(aol_batch_plan* bp, aol_batch_plan::Part& P, const Schedule& sc,
+                                   std::vector<BandStream>& streams) {
+  const int n = (int)P.ids.size();
+  std::vector<BandStream> ps(n);
+  std::vector<const FilterBands*> fbs(n);
+  for (int k = 0; k < n; ++k) fbs[k] = &bp->bands[bp->filt[P.ids[k]]];
   int lds = 0, slots = 0;
-  // The streams share staging buffers sized for the widest, so the launch may
-  // need more LDS than any one stream: narrow the column bands until it fits.
+  // The part's streams share staging buffers sized for the widest, so the
+  // launch may need more LDS than any one stream: narrow the column bands
+  // until it fits.
   for (int budget = sc.budget;;) {
     slots = 0;
-    for (int i = 0; i < bp->n; ++i) {
+    for (int k = 0; k < n; ++k) {
+      const int i = P.ids[k];
       const aol_stream_desc& d = bp->desc[i];
       int l = 0, sl = 0;
-      aol_status st = build_band_stream(bp->bands[bp->filt[i]], d.height, d.width, d.in_pitch, d.out_pitch, 0, sc.seg,
-                                        budget, streams[i], &l, &sl);
+      aol_status st = build_band_stream(*fbs[k], d.height, d.width, d.in_pitch, d.out_pitch, 0, sc.seg, budget, ps[k],
+                                        &l, &sl);
       if (st) return st;
-      streams[i].ptr = i;
+      ps[k].ptr = i;
       slots = std::max(slots, sl);
     }
     std::vector<BandStream*> sp;
-    std::vector<const FilterBands*> fp;
-    for (int i = 0; i < bp->n; ++i) {
-      sp.push_back(&streams[i]);
-      fp.push_back(&bp->bands[bp->filt[i]]);
-    }
-    lds = band_share_staging(sp.data(), fp.data(), bp->n);
+    for (int k = 0; k < n; ++k) sp.push_back(&ps[k]);
+    lds = band_share_staging(sp.data(), fbs.data(), n);
     if (lds <= sc.budget) break;
     budget -= std::max(lds - sc.budget, 1024);
     if (budget < 8 * 1024) return fail(AOL_ERR_UNSUPPORTED, "batch streams do not fit %d bytes of LDS", sc.budget);
   }
   int wg = 0;
-  hipError_t e = band_prepare(bp->elem, slots, bp->split, bp->kmax, (size_t)lds, &wg);
+  hipError_t e = band_prepare(bp->elem, slots, P.split, P.kmax, (size_t)lds, &wg);
   if (e != hipSuccess) return hip_fail(e, "band kernel attributes");
   if (wg < 1) return fail(AOL_ERR_UNSUPPORTED, "batch schedule does not fit a compute unit");
   int dev = 0, cus = 0;
@@ -98,78 +109,97 @@ static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
   // assigned to workgroups by their estimated cost. Segments of the
   // schedule's length (0: about 512 input lines); a stream whose units would
   // each cost more than a workgroup's fair share gets shorter ones.
-  std::vector<const FilterBands*> fbs(bp->n);
-  std::vector<int> segs(bp->n);
-  for (int i = 0; i < bp->n; ++i) {
-    fbs[i] = &bp->bands[bp->filt[i]];
-    const int q = fbs[i]->vb.q;
+  std::vector<int> segs(n);
+  for (int k = 0; k < n; ++k) {
+    const int q = fbs[k]->vb.q;
     const int want = sc.seg > 0 ? sc.seg : 16 * ((512 + 16 * q - 1) / (16 * q));
-    segs[i] = std::max(16, std::min(want, band_max_seg(fbs[i]->vb)));
+    segs[k] = std::max(16, std::min(want, band_max_seg(fbs[k]->vb)));
   }
   std::vector<BandUnit> units;
   std::vector<int64_t> cost;
   for (int round = 0; round < 8; ++round) {
-    band_frame_units(streams.data(), fbs.data(), segs.data(), bp->n, units, cost);
+    band_frame_units(ps.data(), fbs.data(), segs.data(), n, units, cost);
     int64_t total = 0;
     for (int64_t c : cost) total += c;
     const int64_t share = total / std::max<int64_t>(1, std::min<int64_t>((int64_t)wg * cus, (int64_t)units.size()));
     bool cut = false;
-    for (size_t k = 0; k < units.size(); ++k) {
-      const int i = units[k].stream;
-      if (cost[k] > share && segs[i] > 16) {
-        segs[i] = std::max(16, segs[i] / 2 / 16 * 16);
+    for (size_t u = 0; u < units.size(); ++u) {
+      const int k = units[u].stream;
+      if (cost[u] > share && segs[k] > 16) {
+        segs[k] = std::max(16, segs[k] / 2 / 16 * 16);
         cut = true;
-        while (k + 1 < units.size() && units[k + 1].stream == i) ++k;
+        while (u + 1 < units.size() && units[u + 1].stream == k) ++u;
       }
     }
     if (!cut) break;
   }
+  for (BandUnit& U : units) U.stream = P.ids[U.stream];  // index of the whole batch's descriptors
   // the descriptor buffers keep their addresses across schedules (allocated
   // once at full capacity), so a graph captured earlier never reads freed memory
-  if (units.size() > bp->unit_capacity) return fail(AOL_ERR_INVALID, "unit capacity exceeded");
-  if ((e = hipMemcpy(bp->d_streams.ptr, streams.data(), sizeof(BandStream) * streams.size(), hipMemcpyHostToDevice)) !=
-      hipSuccess)
-    return hip_fail(e, "hipMemcpy");
-  if ((e = hipMemcpy(bp->d_units.ptr, units.data(), sizeof(BandUnit) * units.size(), hipMemcpyHostToDevice)) !=
-      hipSuccess)
-    return hip_fail(e, "hipMemcpy");
+  if (units.size() > P.unit_capacity) return fail(AOL_ERR_INVALID, "unit capacity exceeded");
   const int grid = (int)std::min<int64_t>((int64_t)wg * cus, (int64_t)units.size());
   std::vector<int32_t> order, first;
   band_balance(cost, grid, order, first);
-  if ((e = hipMemcpy(bp->d_order.ptr, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice)) !=
+  if ((e = hipMemcpy(P.d_units.ptr, units.data(), sizeof(BandUnit) * units.size(), hipMemcpyHostToDevice)) !=
           hipSuccess ||
-      (e = hipMemcpy(bp->d_first.ptr, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice)) !=
+      (e = hipMemcpy(P.d_order.ptr, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(P.d_first.ptr, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice)) !=
           hipSuccess)
     return hip_fail(e, "hipMemcpy");
+  P.gather = false;
+  for (int k = 0; k < n; ++k) {
+    streams[P.ids[k]] = ps[k];
+    P.gather = P.gather || !ps[k].vec_in;
+  }
+  P.units = std::move(units);
+  P.lds = (size_t)lds;
+  P.slots = slots;
+  P.grid = grid;
+  return AOL_OK;
+}
+
+static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
+  std::vector<BandStream> streams(bp->n);
+  int units = 0, grid = 0, lds = 0, launches = 0;
+  for (aol_batch_plan::Part& P : bp->parts) {
+    if (P.ids.empty()) continue;
+    aol_status st = batch_build_part(bp, P, sc, streams);
+    if (st) return st;
+    units += (int)P.units.size();
+    grid = std::max(grid, P.grid);
+    lds = std::max(lds, (int)P.lds);
+    ++launches;
+  }
+  hipError_t e = hipMemcpy(bp->d_streams.ptr, streams.data(), sizeof(BandStream) * streams.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
   bp->streams = std::move(streams);
-  bp->units = std::move(units);
-  bp->lds = (size_t)lds;
-  bp->slots = slots;
-  bp->grid = grid;
   bp->sched = sc;
-  char buf[160];
-  snprintf(buf, sizeof buf, "{\"seg\": %d, \"lds_budget\": %d, \"units\": %d, \"grid\": %d, \"lds\": %d}",
-           sc.seg, sc.budget, (int)bp->units.size(), bp->grid, lds);
+  char buf[200];
+  snprintf(buf, sizeof buf,
+           "{\"seg\": %d, \"lds_budget\": %d, \"units\": %d, \"grid\": %d, \"lds\": %d, \"launches\": %d}", sc.seg,
+           sc.budget, units, grid, lds, launches);
   bp->sched_json = buf;
   return AOL_OK;
 }
 
 static aol_status batch_launch(aol_batch_plan* bp, hipStream_t stream) {
-  BandLaunch L;
-  memset(&L, 0, sizeof L);
-  L.streams = (const BandStream*)bp->d_streams.ptr;
-  L.units = (const BandUnit*)bp->d_units.ptr;
-  L.units_per_frame = (int32_t)bp->units.size();
-  L.n_frames = 1;
-  L.total_units = (int32_t)bp->units.size();
-  L.aligned = 1;  // checked by aol_batch_set_pointers
-  L.ptr_table = (void* const*)bp->d_table.ptr;
-  L.order = (const int32_t*)bp->d_order.ptr;
-  L.first = (const int32_t*)bp->d_first.ptr;
-  bool gather = false;
-  for (const BandStream& S : bp->streams) gather = gather || !S.vec_in;
-  hipError_t e = band_launch(bp->elem, bp->slots, bp->split, bp->kmax, gather, L, bp->grid, bp->lds, stream);
-  if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+  for (const aol_batch_plan::Part& P : bp->parts) {
+    if (P.ids.empty()) continue;
+    BandLaunch L;
+    memset(&L, 0, sizeof L);
+    L.streams = (const BandStream*)bp->d_streams.ptr;
+    L.units = (const BandUnit*)P.d_units.ptr;
+    L.units_per_frame = (int32_t)P.units.size();
+    L.n_frames = 1;
+    L.total_units = (int32_t)P.units.size();
+    L.aligned = 1;  // checked by aol_batch_set_pointers
+    L.ptr_table = (void* const*)bp->d_table.ptr;
+    L.order = (const int32_t*)P.d_order.ptr;
+    L.first = (const int32_t*)P.d_first.ptr;
+    hipError_t e = band_launch(bp->elem, P.slots, P.split, P.kmax, P.gather, L, P.grid, P.lds, stream);
+    if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+  }
   return AOL_OK;
 }
 
@@ -274,8 +304,8 @@ aol_status aol_batch_plan_create(int32_t n_streams, const aol_stream_desc* strea
     delete bp;
     return st;
   }
-  // filter groups; one kernel instance carries every filter, so if one needs
-  // the split integer taps all of them use the split operand layout
+  // filter groups; the groups that need the split integer taps go to the
+  // second launch
   std::vector<int> rep;
   for (int i = 0; i < n_streams; ++i) {
     int gidx = -1;
@@ -287,23 +317,22 @@ aol_status aol_batch_plan_create(int32_t n_streams, const aol_stream_desc* strea
     }
     bp->filt[i] = gidx;
   }
-  for (int pass = 0; pass < 2; ++pass) {
-    bp->bands.clear();
-    bp->bands.resize(rep.size());
-    bool any_split = false;
-    for (size_t g = 0; g < rep.size(); ++g) {
-      st = build_filter_bands(bp->hf[rep[g]], bp->vf[rep[g]], bp->elem, pass == 1, bp->bands[g]);
-      if (st) {
-        delete bp;
-        return st;
-      }
-      any_split = any_split || bp->bands[g].split;
+  bp->bands.clear();
+  bp->bands.resize(rep.size());
+  for (size_t g = 0; g < rep.size(); ++g) {
+    st = build_filter_bands(bp->hf[rep[g]], bp->vf[rep[g]], bp->elem, false, bp->bands[g]);
+    if (st) {
+      delete bp;
+      return st;
     }
-    bp->split = any_split;
-    if (!any_split || pass == 1) break;
   }
-  bp->kmax = 0;
-  for (const FilterBands& fb : bp->bands) bp->kmax = std::max(bp->kmax, fb.kmax);
+  for (int i = 0; i < n_streams; ++i) {
+    const FilterBands& fb = bp->bands[bp->filt[i]];
+    aol_batch_plan::Part& P = bp->parts[fb.split ? 1 : 0];
+    P.split = fb.split;
+    P.kmax = std::max(P.kmax, fb.kmax);
+    P.ids.push_back(i);
+  }
   bp->key = batch_key(bp);
   Schedule sc;
   if (tune_cache) {
@@ -311,19 +340,23 @@ aol_status aol_batch_plan_create(int32_t n_streams, const aol_stream_desc* strea
     cache_lookup(bp->cache_path, bp->key, &sc);
   }
   // capacity: the most units any schedule can make (bands and segments of 16 repetitions)
-  for (int i = 0; i < n_streams; ++i) {
-    const int64_t rx = (bp->desc[i].width + bp->hf[i].q - 1) / bp->hf[i].q;
-    const int64_t ry = (bp->desc[i].height + bp->vf[i].q - 1) / bp->vf[i].q;
-    bp->unit_capacity += (size_t)(((rx + 15) / 16) * ((ry + 15) / 16));
+  st = AOL_OK;
+  for (aol_batch_plan::Part& P : bp->parts) {
+    for (int i : P.ids) {
+      const int64_t rx = (bp->desc[i].width + bp->hf[i].q - 1) / bp->hf[i].q;
+      const int64_t ry = (bp->desc[i].height + bp->vf[i].q - 1) / bp->vf[i].q;
+      P.unit_capacity += (size_t)(((rx + 15) / 16) * ((ry + 15) / 16));
+    }
+    if (P.unit_capacity > (size_t)INT_MAX / 2) {
+      delete bp;
+      return fail(AOL_ERR_UNSUPPORTED, "too many units");
+    }
+    if (P.ids.empty()) continue;
+    if (!st) st = P.d_units.alloc(sizeof(BandUnit) * P.unit_capacity);
+    if (!st) st = P.d_order.alloc(sizeof(int32_t) * P.unit_capacity);
+    if (!st) st = P.d_first.alloc(sizeof(int32_t) * (P.unit_capacity + 1));
   }
-  if (bp->unit_capacity > (size_t)INT_MAX / 2) {
-    delete bp;
-    return fail(AOL_ERR_UNSUPPORTED, "too many units");
-  }
-  st = bp->d_streams.alloc(sizeof(BandStream) * (size_t)n_streams);
-  if (!st) st = bp->d_units.alloc(sizeof(BandUnit) * bp->unit_capacity);
-  if (!st) st = bp->d_order.alloc(sizeof(int32_t) * bp->unit_capacity);
-  if (!st) st = bp->d_first.alloc(sizeof(int32_t) * (bp->unit_capacity + 1));
+  if (!st) st = bp->d_streams.alloc(sizeof(BandStream) * (size_t)n_streams);
   if (!st) st = batch_build(bp, sc);
   if (!st) st = bp->d_table.alloc(sizeof(void*) * 2 * (size_t)n_streams);
   if (st) {

@@ -16,7 +16,7 @@ MIX = [  # (h, w, p, q, taps, kind)
     (96, 200, 3, 8, 11, "design"),
     (61, 130, 1, 2, 8, "design"),
     (120, 97, 2, 3, 16, "design"),
-    (33, 64, 2, 3, 13, "random"),  # taps beyond int8: split operands for the whole batch
+    (33, 64, 2, 3, 13, "random"),  # taps beyond int8: split operands, run as a second launch
     (250, 330, 3, 8, 16, "design"),
     (17, 19, 1, 2, 9, "random"),
 ]
@@ -129,6 +129,34 @@ def test_batch_64_streams_mix_one_step():
         streams.append((s.h, s.w, filt[key][0], filt[key][0]))
     plan = aol.BatchPlan(streams, "u8")
     g = synthgen.rng_for(2011, 9)
+    frames = [synthgen.gradient_plane(g, s.h, s.w) for s in mix]
+    ins = [torch.from_numpy(f).cuda() for f in frames]
+    outs = [torch.empty(plan.out_shapes[i], dtype=torch.uint8, device="cuda") for i in range(len(mix))]
+    plan.set_pointers(ins, outs)
+    plan.run()
+    torch.cuda.synchronize()
+    for i, s in enumerate(mix):
+        of = filt[(s.p, s.q, s.taps)][1]
+        np.testing.assert_array_equal(outs[i].cpu().numpy(), pp.downscale_u8(frames[i], of, of), err_msg=f"stream {i}")
+    plan.close()
+
+
+def test_batch_int8_taps_streams_of_the_mix():
+    """The streams of the 64-stream mix whose filters fit int8 taps: the fast kernel instance with
+    several filters, sizes and K-step counts in one launch, several units per workgroup."""
+    mix = [s for s in synthgen.stream_mix(2011, 64)
+           if np.abs(np.array(synthgen.design_taps(s.p, s.q, s.taps))).max() <= 127]
+    filt = {}
+    streams = []
+    for s in mix:
+        key = (s.p, s.q, s.taps)
+        if key not in filt:
+            c = synthgen.design_taps(s.p, s.q, s.taps)
+            filt[key] = (aol.Polyphase(s.p, s.q, c), pp.Filter(s.p, s.q, c))
+        streams.append((s.h, s.w, filt[key][0], filt[key][0]))
+    plan = aol.BatchPlan(streams, "u8")
+    assert '"launches": 1' in plan.schedule()
+    g = synthgen.rng_for(2011, 10)
     frames = [synthgen.gradient_plane(g, s.h, s.w) for s in mix]
     ins = [torch.from_numpy(f).cuda() for f in frames]
     outs = [torch.empty(plan.out_shapes[i], dtype=torch.uint8, device="cuda") for i in range(len(mix))]

@@ -111,6 +111,18 @@ def test_unaligned_pitches_and_guard_bytes():
     np.testing.assert_array_equal(Y, pp.downscale_u8(X, of, ov))
 
 
+def test_two_kstep_filters_many_units_per_workgroup():
+    # 3/8 with 16 taps: blocks with one and with two K-steps, column bands, several
+    # units per workgroup (a regression: an unused K-step was accumulated)
+    hf, of = _filters(3, 8, 16)
+    F = 6
+    planes = [synthgen.uniform_frame(31 + f, 1080, 1920, idx=0) for f in range(F)]
+    X = np.stack(planes)
+    (Y,) = _run_u8([X], hf, hf)
+    for f in range(F):
+        np.testing.assert_array_equal(Y[f], pp.downscale_u8(X[f:f + 1], of, of)[0], err_msg=f"frame {f}")
+
+
 @pytest.mark.parametrize("w,out_pad", [(512, 0), (512, 4), (512, 8), (400, 4), (464, 0)])
 def test_output_pitches_paired_stores(w, out_pad):
     # output rows of 192 / 150 / 174 bytes with pitches that are and are not
