@@ -9,7 +9,7 @@ the HBM roofline of the fused kernel, the bf16 matrix-core form of the same
 batch with its max-abs error against the float64 oracle, and the CPU oracle
 timed on a bounded sample on the host's cores.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 5]
+    python bench.py [--gpus 1] [--steps 50] [--warmup 100]
 """
 
 from __future__ import annotations
@@ -159,7 +159,7 @@ BATCH_STREAMS = 64
 BATCH_FRAMES = 30
 
 
-def bench_batch(fmt="u8", steps=BATCH_FRAMES, warmup=3):
+def bench_batch(fmt="u8", steps=BATCH_FRAMES, warmup=BATCH_FRAMES):
     """64 streams of uneven sizes/ratios/taps, 30 frames each; one step = one frame of every
     stream = one pointer-table update + one graph launch of the persistent kernel."""
     import torch
@@ -246,7 +246,7 @@ def bench_batch(fmt="u8", steps=BATCH_FRAMES, warmup=3):
 GEN_SHAPE = (64, 1024, 1024)
 
 
-def bench_generic(steps=10, warmup=2):
+def bench_generic(steps=10, warmup=20):
     """64x1024x1024 float32, random non-identity tiler, 5x5 weighted sum."""
     import torch
     import paper_1103_4881_amd as aol
@@ -344,8 +344,8 @@ def cpu_baseline(n_frames, repeats):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--frames", type=int, default=300)
     ap.add_argument("--cpu-frames", type=int, default=384)
     ap.add_argument("--cpu-repeats", type=int, default=10)
