@@ -111,6 +111,15 @@ def test_unaligned_pitches_and_guard_bytes():
     np.testing.assert_array_equal(Y, pp.downscale_u8(X, of, ov))
 
 
+@pytest.mark.parametrize("p,q,T", [(16, 24, 9), (16, 32, 16)])
+def test_sixteen_blocks_per_period(p, q, T):
+    # p = 16 (the largest): 16 block positions per period shared by the horizontal pass's shares
+    hf, of = _filters(p, q, T)
+    X = synthgen.uniform_frame(17, 100, 240, idx=3)[None]
+    (Y,) = _run_u8([X], hf, hf)
+    np.testing.assert_array_equal(Y, pp.downscale_u8(X, of, of))
+
+
 def test_two_kstep_filters_many_units_per_workgroup():
     # 3/8 with 16 taps: blocks with one and with two K-steps, column bands, several
     # units per workgroup (a regression: an unused K-step was accumulated)
