@@ -59,7 +59,9 @@ template <int PT>
 __device__ __forceinline__ void wsum_box_points(const WsumArgs& a, const float* pb0, int jstep, float (&acc)[PT]) {
 #pragma unroll
   for (int j = 0; j < PT; ++j) acc[j] = 0.f;
-#pragma unroll 1
+  // four pattern elements per iteration: their offsets and weights come in one
+  // batch of scalar loads, and 4*PT box reads are in flight
+#pragma unroll 4
   for (int i = 0; i < a.npat; ++i) {
     const float* p = pb0 + a.offl[i];
     const float w = a.w[i];
