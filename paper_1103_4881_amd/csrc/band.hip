@@ -650,7 +650,7 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
   constexpr int NB = KM <= 2 && !split ? 4 : 1;               // vertical blocks per iteration (operands in flight)
   // horizontal blocks per iteration: about two per share and step at the usual ratios
   constexpr int NBH = NB > 2 ? 2 : NB;
-  constexpr int NBL = KM == 1 && !split && SLOTS <= 4 ? 2 : 1;  // the same for the loading waves
+  constexpr int NBL = 1;  // the loading waves: one (their prefetch holds the registers; measured no slower)
   constexpr int LS = BandLoadShares<split, KM, SLOTS>::value;  // horizontal shares per loading wave
   constexpr int NV = LS * kBandLoadWaves + NW;                 // shares of the horizontal pass
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
