@@ -5,9 +5,18 @@ One step = one pass of the fused horizontal+vertical downscale over a batch
 of 300 synthetic 1920x1080 I420 frames (luma 1920x1080, chroma 960x540,
 3/8 in both directions with 11 taps) resident in HBM, as one launch. The
 JSON line reports output Mpixel/s (luma output pixels, 720x405 per frame),
-the HBM roofline of the fused kernel, the bf16 matrix-core form of the same
-batch with its max-abs error against the float64 oracle, and the CPU oracle
-timed on a bounded sample on the host's cores.
+the HBM roofline of the fused kernel (against the 8 TB/s datasheet figure
+and a copy measured on the same GPU), a bit-exactness check of sampled
+frames of the timed launch against the oracle, and beside it:
+
+  * config1: latency of one 640x480 frame (cache resident, not an HBM figure);
+  * bf16 / fp16: the matrix-core form of the same batch, max-abs error
+    against the float64 oracle per plane and per checked frame;
+  * batch_u8 / batch_bf16: 64 uneven streams, one launch per step in a graph,
+    plus the subset of their 1920x1080 streams;
+  * generic: the 5x5 weighted-sum repetition over a 64x1024x1024 array;
+  * cpu_baseline: the CPU oracle on a bounded sample (all granted cores, one
+    process, and the Array-OL interpreter on the 640x480 frame).
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 100]
 """
@@ -31,6 +40,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 H, W = 1080, 1920
 P, Q, TAPS = 3, 8, 11
 SEED = 20110322
+WARM_SECONDS = 0.5  # launches before every timed region, so the clocks have ramped up
 
 
 def log(*a):
@@ -52,6 +62,10 @@ def alg_bytes_per_frame(in_es, out_es):
     n_in = H * W + 2 * ch * cw
     n_out = oy[0] * oy[1] + 2 * oc[0] * oc[1]
     return n_in * in_es + n_out * out_es, oy
+
+
+def check_frames(n):
+    return sorted({0, n // 2, n - 1})
 
 
 # ------------------------------------------------------------------ HBM traffic from counters
@@ -85,13 +99,23 @@ def traffic_bytes():
 
 # ------------------------------------------------------------------ GPU timing
 
+def warm(launch, warmup, sync):
+    """`warmup` launches, then more until WARM_SECONDS have passed (clock ramp after idle)."""
+    for _ in range(warmup):
+        launch()
+    sync()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < WARM_SECONDS:
+        for _ in range(10):
+            launch()
+        sync()
+
+
 def time_launches(launch, steps, warmup, stream):
     """Warm up, then time `steps` launches: wall clock around them (synchronised on both
     sides) and per-launch HIP events on the launch stream."""
     import torch
-    for _ in range(warmup):
-        launch()
-    torch.cuda.synchronize()
+    warm(launch, warmup, torch.cuda.synchronize)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -105,10 +129,24 @@ def time_launches(launch, steps, warmup, stream):
     return wall / steps * 1e3, float(np.mean(per)), float(np.median(per))
 
 
+def copy_peak(n_bytes=1 << 30, reps=20):
+    """HBM bandwidth of a plain device-to-device copy (torch's copy kernel) on this GPU:
+    2 * n_bytes per launch over the median HIP-event duration."""
+    import torch
+    src = torch.ones(n_bytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    _, _, med = time_launches(lambda: dst.copy_(src), reps, 5, stream)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n_bytes / (med / 1e3) / 1e9
+
+
 def bench_u8(Yh, Uh, Vh, steps, warmup):
     import torch
     import paper_1103_4881_amd as aol
     import synthgen
+    from oracle import polyphase as pp
     n = Yh.shape[0]
     c = synthgen.design_taps(P, Q, TAPS)
     f = aol.Polyphase(P, Q, c)
@@ -117,13 +155,45 @@ def bench_u8(Yh, Uh, Vh, steps, warmup):
     outs = [torch.empty((n,) + s, dtype=torch.uint8, device="cuda") for s in plan.out_shapes]
     stream = torch.cuda.current_stream()
     ms_step, ms_kernel, ms_med = time_launches(lambda: plan.run(ins, outs), steps, warmup, stream)
+    # the timed launch's outputs, sampled frames against the integer oracle (every element)
+    of = pp.Filter(P, Q, c)
+    mism, checked = 0, 0
+    for fr in check_frames(n):
+        for a, o in zip((Yh, Uh, Vh), outs):
+            ref = pp.downscale_u8(a[fr], of, of)
+            mism += int((o[fr].cpu().numpy() != ref).sum())
+            checked += ref.size
     bpf, oy = alg_bytes_per_frame(1, 1)
-    res = dict(ms_step=ms_step, ms_kernel=ms_kernel, ms_kernel_median=ms_med, bytes=bpf * n,
-               out_pixels=n * oy[0] * oy[1], plan=plan, ins=ins, outs=outs)
-    return res
+    return dict(ms_step=ms_step, ms_kernel=ms_kernel, ms_kernel_median=ms_med, bytes=bpf * n,
+                out_pixels=n * oy[0] * oy[1], plan=plan, ins=ins, outs=outs, schedule=plan.schedule(n),
+                mismatches=mism, checked_elements=checked, checked_frames=check_frames(n))
 
 
-def bench_float(ins_u8, steps, warmup, fmt="bf16", check_frames=(0,)):
+def bench_config1(reps=100, warmup=200):
+    """One 640x480 uniform random frame -> 180x240 (3/8, 11 taps): launch latency. The 350 KB
+    working set stays in the caches, so this is a latency figure, not an HBM measurement."""
+    import torch
+    import paper_1103_4881_amd as aol
+    import synthgen
+    from oracle import polyphase as pp
+    X = synthgen.uniform_frame(2024, 480, 640)
+    c = synthgen.design_taps(P, Q, TAPS)
+    f = aol.Polyphase(P, Q, c)
+    plan = aol.DownscalePlan([(480, 640)], f, f, "u8")
+    x = torch.from_numpy(X).cuda()[None]
+    y = torch.empty((1, 180, 240), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    _, mean, med = time_launches(lambda: plan.run([x], [y]), reps, warmup, stream)
+    ok = bool(np.array_equal(y[0].cpu().numpy(), pp.downscale_u8(X, pp.Filter(P, Q, c), pp.Filter(P, Q, c))))
+    sched = plan.schedule(1)
+    plan.close()
+    return {"us_median": round(med * 1e3, 2), "us_mean": round(mean * 1e3, 2), "launches": reps,
+            "out_mpixel_per_s": round(180 * 240 / (med / 1e3) / 1e6, 1), "bit_exact": ok,
+            "note": "one 640x480 frame; 350 KB working set, cache resident: latency, not HBM throughput",
+            "schedule": sched}
+
+
+def bench_float(ins_u8, steps, warmup, fmt="bf16"):
     """The matrix-core form on the same frames: 16-bit normalised pixels in, float32 out."""
     import torch
     import paper_1103_4881_amd as aol
@@ -139,17 +209,30 @@ def bench_float(ins_u8, steps, warmup, fmt="bf16", check_frames=(0,)):
     outs = [torch.empty((n,) + s, dtype=torch.float32, device="cuda") for s in plan.out_shapes]
     stream = torch.cuda.current_stream()
     ms_step, ms_kernel, ms_med = time_launches(lambda: plan.run(ins, outs), steps, warmup, stream)
-    # max-abs error against the float64 oracle on the identical 16-bit inputs
+    # max-abs error against the float64 oracle on the identical 16-bit inputs, per plane and frame
     of = pp.Filter(P, Q, c)
-    errs = []
-    for fr in check_frames:
-        for x16, y in zip(ins, outs):
+    errs = {}
+    for fr in check_frames(n):
+        for name, x16, y in zip("YUV", ins, outs):
             xin = x16[fr].float().cpu().numpy().astype(np.float64)
             ref = pp.downscale_f64(xin, of, of)
-            errs.append(float(np.abs(y[fr].cpu().numpy().astype(np.float64) - ref).max()))
+            errs[f"{name}{fr}"] = float(np.abs(y[fr].cpu().numpy().astype(np.float64) - ref).max())
     bpf, oy = alg_bytes_per_frame(2, 4)
+    plan.close()
+    del ins, outs
+    torch.cuda.empty_cache()
     return dict(ms_step=ms_step, ms_kernel=ms_kernel, ms_kernel_median=ms_med, bytes=bpf * n,
-                out_pixels=n * oy[0] * oy[1], max_abs_err=max(errs), err_frames=list(check_frames))
+                out_pixels=n * oy[0] * oy[1], max_abs_err=max(errs.values()), err_per_plane_frame=errs)
+
+
+def float_entry(fl):
+    fgbs = fl["bytes"] / (fl["ms_kernel"] / 1e3) / 1e9
+    return {"value": round(fl["out_pixels"] / (fl["ms_step"] / 1e3) / 1e6, 1), "unit": "Mpixel/s",
+            "ms_per_step": round(fl["ms_step"], 4), "kernel_ms_median": round(fl["ms_kernel_median"], 4),
+            "max_abs_err": fl["max_abs_err"], "tolerance": 1e-3,
+            "max_abs_err_per_plane_frame": fl["err_per_plane_frame"],
+            "roofline": {"bound": "hbm", "achieved": round(fgbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(fgbs / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": fl["bytes"]}}
 
 
 # ------------------------------------------------------------------ batch of streams
@@ -159,13 +242,17 @@ BATCH_STREAMS = 64
 BATCH_FRAMES = 30
 
 
-def bench_batch(fmt="u8", steps=BATCH_FRAMES, warmup=BATCH_FRAMES):
+def bench_batch(fmt="u8", steps=BATCH_FRAMES, warmup=BATCH_FRAMES, only_size=None):
     """64 streams of uneven sizes/ratios/taps, 30 frames each; one step = one frame of every
-    stream = one pointer-table update + one graph launch of the persistent kernel."""
+    stream = one pointer-table update + one graph launch of the persistent kernel.
+    only_size=(h, w): the subset of the mix's streams of that size."""
     import torch
     import paper_1103_4881_amd as aol
     import synthgen
+    from oracle import polyphase as pp
     mix = synthgen.stream_mix(BATCH_SEED, BATCH_STREAMS)
+    if only_size:
+        mix = [s for s in mix if (s.h, s.w) == tuple(only_size)]
     filt = {}
     streams = []
     for st in mix:
@@ -198,10 +285,9 @@ def bench_batch(fmt="u8", steps=BATCH_FRAMES, warmup=BATCH_FRAMES):
             plan.set_pointer_arrays(tables[k % BATCH_FRAMES], s)
             aol.aol_graph_launch(graph, s)
 
-        for k in range(warmup):
-            step(k)
-        s.synchronize()
+        warm(lambda: step(0), warmup, s.synchronize)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        s.synchronize()
         t0 = time.perf_counter()
         for k, (a, b) in enumerate(ev):
             a.record(s)
@@ -215,18 +301,20 @@ def bench_batch(fmt="u8", steps=BATCH_FRAMES, warmup=BATCH_FRAMES):
     px_step = sum(oh * ow for (oh, ow) in plan.out_shapes)
     ms_step = wall / steps * 1e3
     ms_kernel = float(np.mean(per))
+    ms_med = float(np.median(per))
+    gbs = bytes_step / (ms_kernel / 1e3) / 1e9
     res = {"value": round(px_step / (ms_step / 1e3) / 1e6, 1), "unit": "Mpixel/s", "ms_per_step": round(ms_step, 4),
+           "step_ms_median": round(ms_med, 4), "step_ms_mean": round(ms_kernel, 4),
            "steps": steps, "streams": len(mix), "frames_per_stream": BATCH_FRAMES,
            "bytes_per_step": bytes_step, "out_pixels_per_step": px_step,
-           "roofline": {"bound": "hbm", "achieved": round(bytes_step / (ms_kernel / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(bytes_step / (ms_kernel / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "frac_median": round(bytes_step / (ms_med / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
            "schedule": json.loads(plan.schedule())}
-    # correctness of the last step on a few streams against the oracle
-    from oracle import polyphase as pp
-    k = (warmup + steps - 1) % BATCH_FRAMES
+    # the last step's outputs of every stream against the oracle
+    k = (steps - 1) % BATCH_FRAMES
     errs = []
-    for i in range(0, len(mix), 16):
-        st = mix[i]
+    for i, st in enumerate(mix):
         of = pp.Filter(st.p, st.q, synthgen.design_taps(st.p, st.q, st.taps))
         x = ins[i][k].float().cpu().numpy()
         y = outs[i][k].float().cpu().numpy()
@@ -234,7 +322,7 @@ def bench_batch(fmt="u8", steps=BATCH_FRAMES, warmup=BATCH_FRAMES):
             errs.append(float(np.abs(y - pp.downscale_u8(x.astype(np.uint8), of, of)).max()))
         else:
             errs.append(float(np.abs(y - pp.downscale_f64(x.astype(np.float64), of, of)).max()))
-    res["max_abs_err_sampled_streams"] = max(errs)
+    res["max_abs_err_all_streams"] = max(errs)
     plan.close()
     del ins, outs
     torch.cuda.empty_cache()
@@ -261,14 +349,14 @@ def bench_generic(steps=10, warmup=20):
     x = torch.from_numpy(A).cuda()
     y = torch.empty(plan.out_shape, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
-    ms_step, ms_kernel, _ = time_launches(lambda: plan.run(x, y), steps, warmup, stream)
+    ms_step, ms_kernel, ms_med = time_launches(lambda: plan.run(x, y), steps, warmup, stream)
     # footprint: every input element some pattern element reads (bitmap on the device,
     # a few large batched index computations)
     R = rt.rep_shape
     seen = torch.zeros(int(np.prod(GEN_SHAPE)), dtype=torch.bool, device="cuda")
     S = torch.tensor(GEN_SHAPE, device="cuda").view(3, 1, 1, 1, 1)
     strides = [GEN_SHAPE[1] * GEN_SHAPE[2], GEN_SHAPE[2], 1]
-    P = torch.tensor(rt.paving, device="cuda")
+    Pv = torch.tensor(rt.paving, device="cuda")
     F = torch.tensor(rt.fitting, device="cuda")
     o = torch.tensor(rt.origin, device="cuda")
     pat = torch.stack(torch.meshgrid(torch.arange(5, device="cuda"), torch.arange(5, device="cuda"),
@@ -278,12 +366,13 @@ def bench_generic(steps=10, warmup=20):
     r2 = torch.arange(R[2], device="cuda").view(1, 1, 1, -1, 1)
     for c0 in range(0, R[0], 32):
         r0 = torch.arange(c0, min(c0 + 32, R[0]), device="cuda").view(1, -1, 1, 1, 1)
-        v = (o.view(3, 1, 1, 1, 1) + P[:, 0].view(3, 1, 1, 1, 1) * r0 + P[:, 1].view(3, 1, 1, 1, 1) * r1
-             + P[:, 2].view(3, 1, 1, 1, 1) * r2 + foff)
+        v = (o.view(3, 1, 1, 1, 1) + Pv[:, 0].view(3, 1, 1, 1, 1) * r0 + Pv[:, 1].view(3, 1, 1, 1, 1) * r1
+             + Pv[:, 2].view(3, 1, 1, 1, 1) * r2 + foff)
         v = torch.remainder(v, S)
         flat = v[0] * strides[0] + v[1] * strides[1] + v[2]
         seen[flat.reshape(-1)] = True
     footprint = int(seen.sum().item())
+    del seen
     n_out = int(np.prod(R))
     alg_bytes = 4 * footprint + 4 * n_out
     # sampled parity against the float64 oracle
@@ -295,8 +384,11 @@ def bench_generic(steps=10, warmup=20):
     rel = float((np.abs(got - ref) / np.maximum(mag, 1e-30)).max())
     gbs = alg_bytes / (ms_kernel / 1e3) / 1e9
     plan.close()
+    del x, y
+    torch.cuda.empty_cache()
     return {"value": round(n_out / (ms_step / 1e3) / 1e9, 3), "unit": "Goutput/s", "ms_per_step": round(ms_step, 4),
-            "outputs": n_out, "footprint_elems": footprint, "alg_bytes": alg_bytes,
+            "kernel_ms_median": round(ms_med, 4), "outputs": n_out, "footprint_elems": footprint,
+            "alg_bytes": alg_bytes,
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(gbs / HBM_PEAK_GBS, 4)},
             "max_rel_err_sampled": rel, "tolerance_rel": 1e-5,
@@ -320,12 +412,29 @@ def _cpu_one(i):
     return i
 
 
-def cpu_baseline(n_frames, repeats):
-    """The CPU oracle (vectorised NumPy definition) over a sample of frames, one process per core;
-    the sample is passed `repeats` times so that the timed CPU work lasts 10-30 s."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n_frames, repeats, single_frames):
+    """The CPU oracle (vectorised NumPy definition, one BLAS thread per process) over a sample
+    of frames: one process per granted core (at most 16, the host share of one GPU), the sample
+    passed `repeats` times so the timed CPU work lasts 10-30 s; then one process alone (the
+    analogue of a sequential program) on `single_frames` frames; then the Array-OL interpreter
+    on the 640x480 frame."""
     global _CPU_FRAMES
+    from oracle import polyphase as pp
+    import synthgen
     _CPU_FRAMES = make_frames(n_frames)
-    cores = max(1, min(16, os.cpu_count() or 1))
+    granted = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = max(1, min(16, granted))
     ctx = mp.get_context("fork")
     with ctx.Pool(cores) as pool:
         pool.map(_cpu_one, range(min(cores, n_frames)))  # warm the workers (imports)
@@ -334,9 +443,26 @@ def cpu_baseline(n_frames, repeats):
         dt = time.perf_counter() - t0
     _, oy = alg_bytes_per_frame(1, 1)
     done = n_frames * repeats
+    # one process
+    _cpu_one(0)
+    t0 = time.perf_counter()
+    for i in range(single_frames):
+        _cpu_one(i % n_frames)
+    dt1 = time.perf_counter() - t0
+    # the interpreter (pure Python loops over repetitions) on the 640x480 frame
+    X = synthgen.uniform_frame(2024, 480, 640)
+    f = pp.Filter(P, Q, synthgen.design_taps(P, Q, TAPS))
+    t0 = time.perf_counter()
+    Yi, _, _ = pp.downscale_u8_interp(X, f, f)
+    dti = time.perf_counter() - t0
     return dict(value=done * oy[0] * oy[1] / dt / 1e6, unit="Mpixel/s", cores=cores, kind="oracle",
                 sample=f"{n_frames} I420 1920x1080 frames of the same workload, each downscaled {repeats} times "
-                       f"({done} frames), integer oracle (numpy), {cores} processes, {dt:.1f} s")
+                       f"({done} frames), integer oracle (numpy), {cores} processes, {dt:.1f} s",
+                cpu_model=_cpu_model(), os_cpu_count=os.cpu_count(), granted_cpus=granted,
+                single_process={"value": single_frames * oy[0] * oy[1] / dt1 / 1e6, "unit": "Mpixel/s",
+                                "frames": single_frames, "seconds": round(dt1, 2)},
+                interpreter_config1={"seconds": round(dti, 3), "frame": "640x480 -> 180x240",
+                                     "out_mpixel_per_s": 180 * 240 / dti / 1e6})
 
 
 # ------------------------------------------------------------------ main
@@ -349,9 +475,10 @@ def main():
     ap.add_argument("--frames", type=int, default=300)
     ap.add_argument("--cpu-frames", type=int, default=384)
     ap.add_argument("--cpu-repeats", type=int, default=10)
+    ap.add_argument("--cpu-single-frames", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-float", action="store_true")
-    ap.add_argument("--only", choices=["u8", "bf16", "batch", "generic"], default=None,
+    ap.add_argument("--only", choices=["u8", "bf16", "fp16", "batch", "generic", "config1"], default=None,
                     help="run one workload only (for profiling)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-generic", action="store_true")
@@ -377,36 +504,56 @@ def main():
         sys.exit(2)
 
     cpu = None
-    if not args.no_cpu:  # before the GPU is initialised: the pool forks this process
+    if not args.no_cpu and args.only is None:  # before the GPU is initialised: the pool forks this process
         t = time.time()
-        cpu = cpu_baseline(args.cpu_frames, args.cpu_repeats)
+        cpu = cpu_baseline(args.cpu_frames, args.cpu_repeats, args.cpu_single_frames)
         log(f"cpu baseline in {time.time() - t:.1f} s: {cpu['value']:.1f} Mpixel/s")
 
     import torch
     torch.cuda.set_device(0)
+    out = {"metric": METRIC}
+    extra = {}
+    if args.only is None:
+        extra["copy_peak_gbs"] = round(copy_peak(), 1)
+        log(f"copy: {extra['copy_peak_gbs']} GB/s")
+    if args.only in (None, "config1"):
+        extra["config1"] = bench_config1()
+        log(f"config1: {extra['config1']['us_median']} us")
+        if args.only:
+            print(json.dumps({"metric": METRIC, **extra}), flush=True)
+            return
     t = time.time()
     Yh, Uh, Vh = make_frames(args.frames)
     log(f"generated {args.frames} I420 frames in {time.time() - t:.1f} s")
 
-    out = {"metric": METRIC}
     u8 = None
     if args.only in (None, "u8"):
         u8 = bench_u8(Yh, Uh, Vh, args.steps, args.warmup)
-        log(f"u8 fused: {u8['ms_step']:.3f} ms/step, kernel {u8['ms_kernel']:.3f} ms")
-    fl = None
-    if not args.no_float and args.only in (None, "bf16"):
-        import torch as _t
-        ins_u8 = u8["ins"] if u8 else [_t.from_numpy(a).cuda() for a in (Yh, Uh, Vh)]
+        log(f"u8 fused: {u8['ms_step']:.3f} ms/step, kernel {u8['ms_kernel']:.3f} ms, "
+            f"mismatches {u8['mismatches']}")
+    fl = {}
+    if not args.no_float and args.only in (None, "bf16", "fp16"):
+        ins_u8 = u8["ins"] if u8 else [torch.from_numpy(a).cuda() for a in (Yh, Uh, Vh)]
         if u8:
             del u8["outs"]
-            _t.cuda.empty_cache()
-        fl = bench_float(ins_u8, args.steps, args.warmup, "bf16")
-        log(f"bf16 fused: {fl['ms_step']:.3f} ms/step, kernel {fl['ms_kernel']:.3f} ms, err {fl['max_abs_err']:.2e}")
+            torch.cuda.empty_cache()
+        for fmt in ("bf16", "fp16"):
+            if args.only in (None, fmt):
+                fl[fmt] = bench_float(ins_u8, args.steps, args.warmup, fmt)
+                log(f"{fmt} fused: {fl[fmt]['ms_step']:.3f} ms/step, kernel {fl[fmt]['ms_kernel']:.3f} ms, "
+                    f"err {fl[fmt]['max_abs_err']:.2e}")
+        del ins_u8
+    if u8:
+        u8.pop("ins", None)
+        u8.pop("outs", None)
+        u8["plan"].close()
+        torch.cuda.empty_cache()
 
-    extra = {}
     if not args.no_batch and args.only in (None, "batch"):
         extra["batch_u8"] = bench_batch("u8")
         log(f"batch u8: {extra['batch_u8']['ms_per_step']:.3f} ms/step")
+        extra["batch_u8_1080p_subset"] = bench_batch("u8", only_size=(1080, 1920))
+        log(f"batch u8 1080p subset: {extra['batch_u8_1080p_subset']['ms_per_step']:.3f} ms/step")
         if not args.no_float:
             extra["batch_bf16"] = bench_batch("bf16")
             log(f"batch bf16: {extra['batch_bf16']['ms_per_step']:.3f} ms/step")
@@ -417,10 +564,14 @@ def main():
         print(json.dumps({"metric": METRIC, **extra}), flush=True)
         return
 
-    main_res = u8 if u8 else fl
-    dtype = "u8" if u8 else "bf16"
+    if u8:
+        main_res, dtype = u8, "u8"
+    else:
+        dtype = next(iter(fl))
+        main_res = fl[dtype]
     value = main_res["out_pixels"] / (main_res["ms_step"] / 1e3) / 1e6
     gbs = main_res["bytes"] / (main_res["ms_kernel"] / 1e3) / 1e9
+    copy = extra.get("copy_peak_gbs")
     out.update({
         "value": round(value, 1),
         "unit": "Mpixel/s",
@@ -439,17 +590,19 @@ def main():
         "hbm_frac": round(main_res["bytes"] / (main_res["ms_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic_bytes() if u8 else None,
-                     "kernel": "aol::k_band<u8>" if u8 else "aol::k_band<bf16>",
+                     "copy_peak": copy, "frac_of_copy": round(gbs / copy, 4) if copy else None,
+                     "kernel": "aol::k_band<u8>" if u8 else f"aol::k_band<{dtype}>",
                      "alg_bytes_per_launch": main_res["bytes"],
-                     "kernel_ms_mean": round(main_res["ms_kernel"], 4)},
+                     "kernel_ms_mean": round(main_res["ms_kernel"], 4),
+                     "kernel_ms_median": round(main_res["ms_kernel_median"], 4)},
     })
-    if fl and u8:
-        fgbs = fl["bytes"] / (fl["ms_kernel"] / 1e3) / 1e9
-        out["bf16"] = {"value": round(fl["out_pixels"] / (fl["ms_step"] / 1e3) / 1e6, 1), "unit": "Mpixel/s",
-                       "ms_per_step": round(fl["ms_step"], 4), "max_abs_err": fl["max_abs_err"], "tolerance": 1e-3,
-                       "err_frames": fl["err_frames"],
-                       "roofline": {"bound": "hbm", "achieved": round(fgbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                    "frac": round(fgbs / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": fl["bytes"]}}
+    if u8:
+        out["parity"] = {"mismatches": u8["mismatches"], "checked_elements": u8["checked_elements"],
+                         "checked_frames": u8["checked_frames"], "against": "integer oracle, every element"}
+        out["schedule"] = u8["schedule"]
+    for fmt, res in fl.items():
+        if res is not main_res:
+            out[fmt] = float_entry(res)
     out.update(extra)
     if cpu:
         out["cpu_baseline"] = cpu

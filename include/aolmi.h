@@ -138,17 +138,20 @@ aol_status aol_plan_destroy(aol_plan* plan);
  * lines, tile_ry along columns). tile_rx*hf.q must be a multiple of 16 elements (U8) or 8
  * (float); at most 512 outputs per tile and axis. AOL_ERR_INVALID for a
  * misaligned tile, AOL_ERR_UNSUPPORTED if it would not fit the chip's shared
- * memory. Optional: plans start with about 128 input pixels per tile side. */
+ * memory. Optional: plans start with about 128 input pixels per tile side.
+ * Rebuilds the plan's tables like aol_plan_set_band (capture graphs again). */
 aol_status aol_plan_set_tile(aol_plan* plan, int32_t tile_rx, int32_t tile_ry);
 
 /* Band schedule (the default for every plan that fits it): a workgroup owns a
  * column band of band_reps repetitions (0: the widest that fits a compute
  * unit, normally the full width) and streams segments of seg_reps
  * repetitions down the plane, keeping the intermediate in an LDS ring.
- * seg_reps 0: chosen at the first launch with a given frame count (the
- * longest of about 512 ... 64 input lines that leaves every workgroup a few
- * units; that launch copies the schedule to the device on its stream).
- * Multiples of 16. Selecting a band re-selects the band kernel after
+ * seg_reps 0: the plan keeps unit lists for segments of about 512, 256, 128
+ * and 64 input lines, and each launch takes the longest that leaves every
+ * resident workgroup about four units. Multiples of 16. This call (like plan
+ * creation) builds and uploads those lists synchronously; it frees the
+ * previous ones, so a graph captured from an earlier run of this plan must
+ * be captured again. Selecting a band re-selects the band kernel after
  * aol_plan_set_tile. AOL_ERR_UNSUPPORTED if the band does not fit. Results
  * are identical for every schedule. */
 aol_status aol_plan_set_band(aol_plan* plan, int32_t band_reps, int32_t seg_reps);
@@ -157,6 +160,11 @@ aol_status aol_plan_set_band(aol_plan* plan, int32_t band_reps, int32_t seg_reps
  * plane: 0 = row-major (horizontal neighbours consecutive, the default),
  * 1 = column-major. A schedule choice only; results are identical. */
 aol_status aol_plan_set_walk(aol_plan* plan, int32_t order);
+
+/* The schedule a launch of n_frames frames uses, as a JSON object (kernel,
+ * segment length, units per frame, items, grid, LDS bytes); plan-owned text,
+ * valid until the next call on the plan. "" for a NULL plan. */
+const char* aol_plan_schedule(aol_plan* plan, int32_t n_frames);
 
 /* Integer path (plan precision AOL_PREC_U8). For plane j, d_in[j] points to
  * frame 0 of n_frames frames spaced in_frame_stride[j] elements apart, and
@@ -215,8 +223,9 @@ aol_status aol_batch_set_pointers(aol_batch_plan* plan, const void* const* d_in,
 aol_status aol_batch_run(aol_batch_plan* plan, hipStream_t stream);
 
 /* Capture one aol_batch_run into a graph (stream must not be the default
- * stream). Graphs read the pointer table at run time; re-create them after
- * aol_autotune, which changes the launch. */
+ * stream). Graphs read the pointer table at run time. aol_autotune changes
+ * the launch: aol_graph_launch returns AOL_ERR_INVALID for a graph captured
+ * before it (capture again), and for a graph whose plan was destroyed. */
 aol_status aol_batch_graph_create(aol_batch_plan* plan, hipStream_t stream, aol_graph** out);
 aol_status aol_graph_launch(aol_graph* graph, hipStream_t stream);
 aol_status aol_graph_destroy(aol_graph* graph);
@@ -225,6 +234,16 @@ aol_status aol_graph_destroy(aol_graph* graph);
  * on the buffers last set, keeps the fastest, and appends it to the tuning
  * cache. Synchronises the stream (not a run call); results are unchanged. */
 aol_status aol_autotune(aol_batch_plan* plan, hipStream_t stream);
+
+/* Rebuilds the plan with one schedule: segments of seg_reps repetitions (a
+ * multiple of 16; 0: about 512 input lines, shortened for streams whose units
+ * would exceed a workgroup's fair share) and column bands that fit
+ * lds_budget bytes of LDS per workgroup (16 KiB .. 160 KiB). A configuration
+ * call (synchronous uploads), not a run call; graphs captured before it must
+ * be captured again. AOL_ERR_UNSUPPORTED when the schedule does not fit; the
+ * previous schedule stays in place. Results are identical for every
+ * schedule. */
+aol_status aol_batch_set_schedule(aol_batch_plan* plan, int32_t seg_reps, int32_t lds_budget);
 
 /* The plan's current schedule as a JSON object (plan-owned string). */
 const char* aol_batch_schedule(aol_batch_plan* plan);
@@ -271,6 +290,14 @@ aol_status aol_wsum_plan_create(const aol_tiler* in, const aol_tiler* out, const
  * array (prod(out->array_shape) floats). Enqueue only. */
 aol_status aol_wsum_run(aol_wsum_plan* plan, const float* d_in, float* d_out, hipStream_t stream);
 aol_status aol_wsum_plan_destroy(aol_wsum_plan* plan);
+
+/* One-shot form of the above: validates both tilers (the bijection check of a
+ * non-identity output tiler walks the repetition space on the host) and
+ * enqueues the launch on stream. The weights travel in the kernel arguments,
+ * so nothing is allocated on the device; same limits and errors as
+ * aol_wsum_plan_create and aol_wsum_run. */
+aol_status aol_weighted_sum_f32(const aol_tiler* in, const aol_tiler* out, const float* weights, const float* d_in,
+                                float* d_out, hipStream_t stream);
 
 #ifdef __cplusplus
 }

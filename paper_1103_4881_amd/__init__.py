@@ -86,6 +86,7 @@ _proto("aol_plan_destroy", ctypes.c_int, ctypes.c_void_p)
 _proto("aol_plan_set_tile", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32)
 _proto("aol_plan_set_walk", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32)
 _proto("aol_plan_set_band", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32)
+_proto("aol_plan_schedule", ctypes.c_char_p, ctypes.c_void_p, ctypes.c_int32)
 _proto("aol_downscale_u8", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), c_i64p,
        ctypes.POINTER(ctypes.c_void_p), c_i64p, ctypes.c_void_p)
 _proto("aol_downscale_f", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), c_i64p,
@@ -108,6 +109,7 @@ _proto("aol_graph_launch", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
 _proto("aol_graph_destroy", ctypes.c_int, ctypes.c_void_p)
 _proto("aol_autotune", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
 _proto("aol_batch_schedule", ctypes.c_char_p, ctypes.c_void_p)
+_proto("aol_batch_set_schedule", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32)
 
 
 class aol_tiler(ctypes.Structure):
@@ -122,6 +124,8 @@ _proto("aol_wsum_plan_create", ctypes.c_int, ctypes.POINTER(aol_tiler), ctypes.P
        ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_void_p))
 _proto("aol_wsum_run", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 _proto("aol_wsum_plan_destroy", ctypes.c_int, ctypes.c_void_p)
+_proto("aol_weighted_sum_f32", ctypes.c_int, ctypes.POINTER(aol_tiler), ctypes.POINTER(aol_tiler),
+       ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
 
 def _check(status: int):
@@ -211,6 +215,10 @@ def aol_plan_set_walk(plan, order: int):
     _check(_lib.aol_plan_set_walk(plan, order))
 
 
+def aol_plan_schedule(plan, n_frames: int) -> str:
+    return _lib.aol_plan_schedule(plan, int(n_frames)).decode()
+
+
 def _ptrs(vals):
     return (ctypes.c_void_p * len(vals))(*[int(v) for v in vals])
 
@@ -256,6 +264,11 @@ class DownscalePlan:
 
     def set_walk(self, order: int):
         aol_plan_set_walk(self._h, order)
+
+    def schedule(self, n_frames: int) -> dict:
+        """The schedule a launch over ``n_frames`` frames uses."""
+        import json
+        return json.loads(aol_plan_schedule(self._h, n_frames))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -344,6 +357,14 @@ def aol_wsum_plan_destroy(plan):
     _check(_lib.aol_wsum_plan_destroy(plan))
 
 
+def aol_weighted_sum_f32(tin: aol_tiler, tout: aol_tiler, weights, d_in, d_out, stream=None):
+    """One-shot weighted-sum repetition (no plan; the weights go in the kernel arguments)."""
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+    _check(_lib.aol_weighted_sum_f32(ctypes.byref(tin), ctypes.byref(tout),
+                                     w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                     ctypes.c_void_p(int(d_in)), ctypes.c_void_p(int(d_out)), _stream_handle(stream)))
+
+
 class WeightedSumPlan:
     """``out[(o' + P'.r) mod S'] = sum_i w[i] * in[(o + P.r + F.i) mod S]`` on float32 device tensors."""
 
@@ -427,6 +448,10 @@ def aol_batch_schedule(plan) -> str:
     return _lib.aol_batch_schedule(plan).decode()
 
 
+def aol_batch_set_schedule(plan, seg_reps: int, lds_budget: int):
+    _check(_lib.aol_batch_set_schedule(plan, int(seg_reps), int(lds_budget)))
+
+
 class BatchPlan:
     """Many streams, one frame each per step, one persistent launch (optionally a graph)."""
 
@@ -476,6 +501,9 @@ class BatchPlan:
 
     def schedule(self) -> str:
         return aol_batch_schedule(self._h)
+
+    def set_schedule(self, seg_reps: int, lds_budget: int):
+        aol_batch_set_schedule(self._h, seg_reps, lds_budget)
 
     def close(self):
         for g in self._graphs:

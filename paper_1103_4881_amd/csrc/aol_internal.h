@@ -147,6 +147,7 @@ struct BandLaunch {
   const BandUnit* units;         // the units of one frame
   // Unit ids (frame * units_per_frame + unit) grouped by workgroup:
   // workgroup g takes order[first[g]], ..., order[first[g + 1] - 1], in turn.
+  // NULL: the kernel deals the frames' units to the workgroups in rounds.
   const int32_t* order;
   const int32_t* first;
   int32_t units_per_frame, n_frames, total_units;

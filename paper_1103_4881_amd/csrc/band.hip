@@ -461,15 +461,33 @@ __device__ __forceinline__ void band_unit(const BandLaunch& L, int u, BandStream
   G.vec_out = S.vec_out && L.aligned;
 }
 
-// Workgroup's share of the launch: positions [i0, i1) of the unit order.
+// Workgroup's share of the launch: positions [i0, i1) of its sequence of
+// units. With a unit order (batches) the sequence is its slice of that
+// table. Without one (downscale plans) the launch's items, the units of one
+// frame most expensive first, each repeated over the frames (item x is unit
+// x / n_frames of frame x mod n_frames), are dealt in rounds of one per
+// workgroup, every other round in reverse order, so that each workgroup
+// gets a similar mix of long and short units whatever the frame count.
 __device__ __forceinline__ void band_share(const BandLaunch& L, int& i0, int& i1) {
-  const AOL_CONST int32_t* f = (const AOL_CONST int32_t*)L.first + blockIdx.x;
-  i0 = f[0];
-  i1 = f[1];
+  if (L.order) {
+    const AOL_CONST int32_t* f = (const AOL_CONST int32_t*)L.first + blockIdx.x;
+    i0 = f[0];
+    i1 = f[1];
+  } else {
+    const int G = gridDim.x, g = blockIdx.x;
+    const int full = L.total_units / G, rem = L.total_units - full * G;
+    const int pos = (full & 1) ? G - 1 - g : g;  // position in the last, partial round
+    i0 = 0;
+    i1 = full + (pos < rem ? 1 : 0);
+  }
 }
 
 __device__ __forceinline__ int band_unit_at(const BandLaunch& L, int i) {
-  return ((const AOL_CONST int32_t*)L.order)[i];
+  if (L.order) return ((const AOL_CONST int32_t*)L.order)[i];
+  const int G = gridDim.x, g = blockIdx.x;
+  const int x = i * G + ((i & 1) ? G - 1 - g : g);  // item of round i
+  const int unit = x / L.n_frames, frame = x - unit * L.n_frames;
+  return frame * L.units_per_frame + unit;
 }
 
 // Stream descriptor of unit u (the loading waves need the next unit's

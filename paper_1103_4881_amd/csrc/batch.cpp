@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -60,11 +61,19 @@ struct aol_batch_plan {
   DeviceBuf d_streams, d_table;
   bool pointers_set = false;
   std::string cache_path, key, sched_json;
+  // Incremented by every schedule rebuild; set to kGone when the plan is
+  // destroyed. Shared with the plan's graphs, which refuse to launch once it
+  // differs from the value they captured.
+  std::shared_ptr<uint64_t> generation = std::make_shared<uint64_t>(0);
+  static constexpr uint64_t kGone = ~0ull;
+  ~aol_batch_plan() { *generation = kGone; }
 };
 
 struct aol_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  std::shared_ptr<uint64_t> plan_generation;
+  uint64_t captured = 0;
 };
 
 // One part's streams, units and balanced order for a schedule.
@@ -135,7 +144,9 @@ static aol_status batch_build_part(aol_batch_plan* bp, aol_batch_plan::Part& P, 
   }
   for (BandUnit& U : units) U.stream = P.ids[U.stream];  // index of the whole batch's descriptors
   // the descriptor buffers keep their addresses across schedules (allocated
-  // once at full capacity), so a graph captured earlier never reads freed memory
+  // once at full capacity); a graph captured before a rebuild would still run
+  // its old grid and kernel instance over the new tables, so aol_graph_launch
+  // refuses it (the plan's generation changes below)
   if (units.size() > P.unit_capacity) return fail(AOL_ERR_INVALID, "unit capacity exceeded");
   const int grid = (int)std::min<int64_t>((int64_t)wg * cus, (int64_t)units.size());
   std::vector<int32_t> order, first;
@@ -160,6 +171,7 @@ static aol_status batch_build_part(aol_batch_plan* bp, aol_batch_plan::Part& P, 
 }
 
 static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
+  ++*bp->generation;  // first: a build that fails halfway has already rewritten tables
   std::vector<BandStream> streams(bp->n);
   int units = 0, grid = 0, lds = 0, launches = 0;
   for (aol_batch_plan::Part& P : bp->parts) {
@@ -421,12 +433,18 @@ aol_status aol_batch_graph_create(aol_batch_plan* plan, hipStream_t stream, aol_
     delete g;
     return hip_fail(e, "hipGraphInstantiate");
   }
+  g->plan_generation = plan->generation;
+  g->captured = *plan->generation;
   *out = g;
   return ok();
 }
 
 aol_status aol_graph_launch(aol_graph* graph, hipStream_t stream) {
   if (!graph || !graph->exec) return fail(AOL_ERR_INVALID, "NULL graph");
+  if (*graph->plan_generation != graph->captured)
+    return fail(AOL_ERR_INVALID, *graph->plan_generation == aol_batch_plan::kGone
+                                     ? "the graph's batch plan was destroyed"
+                                     : "the batch plan's schedule changed (aol_autotune) since this graph was captured");
   hipError_t e = hipGraphLaunch(graph->exec, stream);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   return ok();
@@ -482,6 +500,24 @@ aol_status aol_autotune(aol_batch_plan* plan, hipStream_t stream) {
   if (st) return st;
   if ((st = batch_build(plan, best))) return st;
   if (!plan->cache_path.empty()) cache_store(plan->cache_path, plan->key, best);
+  return ok();
+}
+
+aol_status aol_batch_set_schedule(aol_batch_plan* plan, int32_t seg_reps, int32_t lds_budget) {
+  if (!plan) return fail(AOL_ERR_INVALID, "NULL plan");
+  if (seg_reps < 0 || seg_reps % 16) return fail(AOL_ERR_INVALID, "seg_reps must be a multiple of 16 (or 0)");
+  if (lds_budget < 16 * 1024 || lds_budget > 160 * 1024)
+    return fail(AOL_ERR_INVALID, "lds_budget must be within 16 KiB .. 160 KiB");
+  Schedule sc;
+  sc.seg = seg_reps;
+  sc.budget = lds_budget;
+  aol_status st = batch_build(plan, sc);
+  if (st) {
+    const std::string msg = last_error();
+    const Schedule old = plan->sched;
+    if (batch_build(plan, old) != AOL_OK) return fail(AOL_ERR_HIP, "restoring the previous schedule failed");
+    return fail(st, "%s", msg.c_str());
+  }
   return ok();
 }
 

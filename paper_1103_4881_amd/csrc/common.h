@@ -12,6 +12,7 @@ namespace aol {
 aol_status fail(aol_status st, const char* fmt, ...);
 aol_status ok();
 aol_status hip_fail(hipError_t e, const char* what);
+const char* last_error();
 
 // One axis' filter as validated host data.
 struct FilterHost {

@@ -326,4 +326,14 @@ aol_status aol_wsum_plan_destroy(aol_wsum_plan* plan) {
   return ok();
 }
 
+aol_status aol_weighted_sum_f32(const aol_tiler* in, const aol_tiler* out, const float* weights, const float* d_in,
+                                float* d_out, hipStream_t stream) {
+  aol_wsum_plan* plan = nullptr;
+  aol_status st = aol_wsum_plan_create(in, out, weights, &plan);
+  if (st) return st;
+  st = aol_wsum_run(plan, d_in, d_out, stream);  // the plan holds host data only: freed at once
+  delete plan;
+  return st;
+}
+
 }  // extern "C"

@@ -270,16 +270,16 @@ struct aol_plan {
   FilterBands fbands;
   BandStream bstreams[kMaxPlanes];
   DeviceBuf d_bstreams;
-  // Units (of one frame) and their balanced order, per frame count launched
-  // so far. Kept until the plan is destroyed: a graph that captured a launch
-  // copies from the host arrays.
+  // Unit lists of one frame for the candidate segment lengths, longest
+  // segments first, each sorted by decreasing estimated cost. Built with the
+  // band schedule (plan creation, aol_plan_set_band); a launch only picks one.
   struct BandSched {
-    int frames = 0;
-    std::vector<BandUnit> units;
-    std::vector<int32_t> order, first;
-    DeviceBuf d_units, d_order, d_first;
+    int seg = 0;    // repetitions per segment
+    int units = 0;  // units per frame
+    DeviceBuf d_units;
   };
-  std::vector<std::unique_ptr<BandSched>> bsched;
+  std::vector<BandSched> bsched;
+  std::string sched_json;  // text returned by aol_plan_schedule
   bool split = false;
   DeviceBuf d_hb, d_vb, d_hfrag, d_vfrag;
 };
@@ -424,56 +424,45 @@ static aol_status plan_build_band(aol_plan* pl, int xreps, int seg) {
     return hip_fail(e, "hipDeviceGetAttribute");
   DeviceBuf ds;
   if ((st = ds.upload(pl->bstreams, sizeof(BandStream) * pl->n_planes))) return st;
+  // Segment lengths: the requested one, else about 512, 256, 128 and 64 input
+  // lines. Each list holds the units of one frame, most expensive first: a
+  // launch over n frames hands its n * units items to the workgroups in
+  // rounds (see k_band), so the list never depends on the frame count.
+  std::vector<aol_plan::BandSched> scheds;
+  {
+    const FilterBands* fbs[kMaxPlanes];
+    for (int i = 0; i < pl->n_planes; ++i) fbs[i] = &fb;
+    const AxisBand& vb = fb.vb;
+    for (int lines = 512; lines >= 64; lines /= 2) {
+      int sg = seg > 0 ? seg : 16 * ((lines + 16 * vb.q - 1) / (16 * vb.q));
+      sg = std::max(16, std::min(sg, band_max_seg(vb)));
+      if (!scheds.empty() && scheds.back().seg == sg) continue;
+      int segs[kMaxPlanes];
+      for (int i = 0; i < pl->n_planes; ++i) segs[i] = sg;
+      std::vector<BandUnit> units;
+      std::vector<int64_t> cost;
+      band_frame_units(pl->bstreams, fbs, segs, pl->n_planes, units, cost);
+      std::vector<int> idx(units.size());
+      for (size_t u = 0; u < idx.size(); ++u) idx[u] = (int)u;
+      std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+      std::vector<BandUnit> sorted;
+      for (int u : idx) sorted.push_back(units[u]);
+      aol_plan::BandSched sc;
+      sc.seg = sg;
+      sc.units = (int)sorted.size();
+      if ((st = sc.d_units.upload(sorted.data(), sizeof(BandUnit) * sorted.size()))) return st;
+      scheds.push_back(std::move(sc));
+      if (seg > 0) break;
+    }
+  }
   pl->fbands = std::move(fb);  // moves ownership; the device addresses in the streams stay valid
   pl->d_bstreams = std::move(ds);
   pl->bseg = seg;
-  pl->bsched.clear();
+  pl->bsched = std::move(scheds);
   pl->bslots = slots;
   pl->blds = (size_t)lds;
   pl->bgrid = wg * cus;
   pl->use_band = true;
-  return AOL_OK;
-}
-
-// Segment length of each plane for a launch of n_frames frames: the
-// requested one, else the longest of about 512, 256, 128, 64 input lines that
-// still gives every resident workgroup a few units to balance.
-static aol_status band_plan_schedule(aol_plan* plan, int n_frames, hipStream_t stream) {
-  const FilterBands* fbs[kMaxPlanes];
-  for (int i = 0; i < plan->n_planes; ++i) fbs[i] = &plan->fbands;
-  const AxisBand& vb = plan->fbands.vb;
-  auto ns = std::make_unique<aol_plan::BandSched>();
-  ns->frames = n_frames;
-  std::vector<int64_t> frame_cost;
-  for (int lines = 512;; lines /= 2) {
-    int seg = plan->bseg > 0 ? plan->bseg : 16 * ((lines + 16 * vb.q - 1) / (16 * vb.q));
-    seg = std::max(16, std::min(seg, band_max_seg(vb)));
-    int segs[kMaxPlanes];
-    for (int i = 0; i < plan->n_planes; ++i) segs[i] = seg;
-    band_frame_units(plan->bstreams, fbs, segs, plan->n_planes, ns->units, frame_cost);
-    if (plan->bseg > 0 || lines <= 64 || (int64_t)ns->units.size() * n_frames >= 4 * (int64_t)plan->bgrid) break;
-  }
-  const int64_t total = (int64_t)ns->units.size() * n_frames;
-  if (total > INT_MAX) return fail(AOL_ERR_UNSUPPORTED, "too many units in one launch");
-  std::vector<int64_t> cost((size_t)total);
-  for (int f = 0; f < n_frames; ++f)
-    std::copy(frame_cost.begin(), frame_cost.end(), cost.begin() + (size_t)f * ns->units.size());
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, plan->bgrid));
-  band_balance(cost, grid, ns->order, ns->first);
-  aol_status st = ns->d_units.alloc(sizeof(BandUnit) * ns->units.size());
-  if (!st) st = ns->d_order.alloc(sizeof(int32_t) * ns->order.size());
-  if (!st) st = ns->d_first.alloc(sizeof(int32_t) * ns->first.size());
-  if (st) return st;
-  hipError_t e = hipMemcpyAsync(ns->d_units.ptr, ns->units.data(), sizeof(BandUnit) * ns->units.size(),
-                                hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(ns->d_order.ptr, ns->order.data(), sizeof(int32_t) * ns->order.size(),
-                       hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(ns->d_first.ptr, ns->first.data(), sizeof(int32_t) * ns->first.size(),
-                       hipMemcpyHostToDevice, stream);
-  if (e != hipSuccess) return hip_fail(e, "unit schedule upload");
-  plan->bsched.push_back(std::move(ns));
   return AOL_OK;
 }
 
@@ -604,6 +593,14 @@ aol_status aol_plan_set_tile(aol_plan* plan, int32_t tile_rx, int32_t tile_ry) {
 
 }  // extern "C"
 
+// The longest segments that still give every resident workgroup about four
+// units (the lists were built with the plan).
+static const aol_plan::BandSched* band_pick_sched(const aol_plan* plan, int n_frames) {
+  for (const auto& x : plan->bsched)
+    if ((int64_t)x.units * n_frames >= 4 * (int64_t)plan->bgrid) return &x;
+  return &plan->bsched.back();
+}
+
 static aol_status run_fused(aol_plan* plan, int32_t n_frames, const void* const* d_in, const int64_t* in_fs,
                             void* const* d_out, const int64_t* out_fs, hipStream_t stream, int out_es) {
   if (n_frames < 0) return fail(AOL_ERR_INVALID, "n_frames < 0");
@@ -663,22 +660,15 @@ static aol_status run_fused(aol_plan* plan, int32_t n_frames, const void* const*
     L.aligned = aligned ? 1 : 0;
     bool gather = !aligned;
     for (int i = 0; i < plan->n_planes; ++i) gather = gather || !plan->bstreams[i].vec_in;
-    // The units and their balanced order for this frame count, built and
-    // copied to the device on the stream at the first launch with it.
-    aol_plan::BandSched* sc = nullptr;
-    for (auto& x : plan->bsched)
-      if (x->frames == n_frames) sc = x.get();
-    if (!sc) {
-      aol_status st = band_plan_schedule(plan, n_frames, stream);
-      if (st) return st;
-      sc = plan->bsched.back().get();
-    }
+    const aol_plan::BandSched* sc = band_pick_sched(plan, n_frames);
+    const int64_t items = (int64_t)sc->units * n_frames;
+    if (items > INT_MAX) return fail(AOL_ERR_UNSUPPORTED, "too many units in one launch");
     L.units = (const BandUnit*)sc->d_units.ptr;
-    L.units_per_frame = (int32_t)sc->units.size();
-    L.total_units = L.units_per_frame * n_frames;
-    L.order = (const int32_t*)sc->d_order.ptr;
-    L.first = (const int32_t*)sc->d_first.ptr;
-    const int grid = (int)sc->first.size() - 1;
+    L.units_per_frame = sc->units;
+    L.total_units = (int32_t)items;
+    L.order = nullptr;  // rounds over the workgroups, computed in the kernel
+    L.first = nullptr;
+    const int grid = (int)std::min<int64_t>(items, plan->bgrid);
     hipError_t e = band_launch(plan->elem, plan->bslots, plan->fbands.split, plan->fbands.kmax, gather, L, grid,
                                plan->blds, stream);
     if (e != hipSuccess) return hip_fail(e, "band kernel launch");
@@ -717,6 +707,25 @@ aol_status aol_downscale_u8(aol_plan* plan, int32_t n_frames, const uint8_t* con
   if (plan->elem != kU8) return fail(AOL_ERR_INVALID, "plan precision is not AOL_PREC_U8");
   return run_fused(plan, n_frames, (const void* const*)d_in, in_frame_stride, (void* const*)d_out, out_frame_stride,
                    stream, 1);
+}
+
+const char* aol_plan_schedule(aol_plan* plan, int32_t n_frames) {
+  if (!plan) return "";
+  char buf[320];
+  if (plan->use_band) {
+    const aol_plan::BandSched* sc = band_pick_sched(plan, std::max(1, (int)n_frames));
+    const int64_t items = (int64_t)sc->units * std::max(1, (int)n_frames);
+    snprintf(buf, sizeof buf,
+             "{\"kernel\": \"band\", \"seg\": %d, \"units_per_frame\": %d, \"items\": %lld, \"grid\": %lld, "
+             "\"slots\": %d, \"kmax\": %d, \"split\": %d, \"lds\": %zu}",
+             sc->seg, sc->units, (long long)items, (long long)std::min<int64_t>(items, plan->bgrid), plan->bslots,
+             plan->fbands.kmax, plan->fbands.split ? 1 : 0, plan->blds);
+  } else {
+    snprintf(buf, sizeof buf, "{\"kernel\": \"tiled\", \"tile\": [%d, %d], \"lds\": %zu}", plan->trx, plan->try_,
+             plan->lds);
+  }
+  plan->sched_json = buf;
+  return plan->sched_json.c_str();
 }
 
 aol_status aol_downscale_f(aol_plan* plan, int32_t n_frames, const void* const* d_in, const int64_t* in_frame_stride,

@@ -116,3 +116,23 @@ def test_batch_validation_on_host():
     _expect(aol.AOL_ERR_UNSUPPORTED, aol.aol_batch_plan_create, [(64, 64, good, good), (64, 64, bad, good)], "u8")
     _expect(aol.AOL_ERR_INVALID, aol.aol_batch_plan_create, [(64, 64, good, good, 10, 0)], "u8")
     _expect(aol.AOL_ERR_INVALID, aol.aol_batch_run, None, 0)
+
+
+def test_one_shot_weighted_sum_validation_on_host():
+    """aol_weighted_sum_f32 validates both tilers and the buffers before any launch (stream 0:
+    no device is touched)."""
+    w = np.ones(9, np.float32)
+    good = aol.make_tiler((8, 8), (8, 8), (3, 3), (0, 0), [[1, 0], [0, 1]], [[1, 0], [0, 1]])
+    ident = aol.identity_out_tiler((8, 8))
+    clash = aol.make_tiler((8, 8), (8, 8), (), (0, 0), [[0, 0], [0, 1]], np.zeros((2, 0), np.int64))
+    _expect(aol.AOL_ERR_INVALID, aol.aol_weighted_sum_f32, good, clash, w, 16, 16, 0)
+    _expect(aol.AOL_ERR_INVALID, aol.aol_weighted_sum_f32, good, aol.identity_out_tiler((8, 7)), w, 16, 16, 0)
+    big = aol.make_tiler((8, 8), (8, 8), (9, 9), (0, 0), [[1, 0], [0, 1]], [[1, 0], [0, 1]])
+    _expect(aol.AOL_ERR_UNSUPPORTED, aol.aol_weighted_sum_f32, big, ident, np.ones(81, np.float32), 16, 16, 0)
+    _expect(aol.AOL_ERR_INVALID, aol.aol_weighted_sum_f32, good, ident, w, 0, 16, 0)  # NULL input
+    _expect(aol.AOL_ERR_INVALID, aol.aol_weighted_sum_f32, good, ident, w, 18, 16, 0)  # misaligned input
+
+
+def test_schedule_calls_reject_null_plans():
+    _expect(aol.AOL_ERR_INVALID, aol.aol_batch_set_schedule, None, 0, 150 * 1024)
+    assert aol.aol_plan_schedule(None, 1) == ""

@@ -8,9 +8,12 @@ import pytest
 import synthgen
 from oracle import polyphase as pp
 
-torch = pytest.importorskip("torch")
+import torch
+
+import paper_1103_4881_amd as aol  # a missing library fails the suite (no skip)
+
 pytestmark = pytest.mark.gpu
-aol = pytest.importorskip("paper_1103_4881_amd")
+FILLS = (0x00, 0xFF)  # output sentinels: an element left unwritten differs between the two runs
 
 MIX = [  # (h, w, p, q, taps, kind)
     (96, 200, 3, 8, 11, "design"),
@@ -45,13 +48,14 @@ def _frames(mix, n, seed):
     return [[synthgen.uniform_frame(seed + f, h, w, idx=i) for f in range(n)] for i, (h, w, *_) in enumerate(mix)]
 
 
-def test_batch_u8_run_and_graph_bit_exact():
+@pytest.mark.parametrize("fill", FILLS)
+def test_batch_u8_run_and_graph_bit_exact(fill):
     st = _streams(MIX)
     plan = aol.BatchPlan([(h, w, hf, vf) for (h, w, hf, vf, _, _) in st], "u8")
     steps = 3
     frames = _frames(MIX, steps, 7)
     ins = [[torch.from_numpy(fr).cuda() for fr in fs] for fs in frames]
-    outs = [[torch.full(plan.out_shapes[i], 0xA5, dtype=torch.uint8, device="cuda") for _ in range(steps)]
+    outs = [[torch.full(plan.out_shapes[i], fill, dtype=torch.uint8, device="cuda") for _ in range(steps)]
             for i in range(len(st))]
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
@@ -73,13 +77,14 @@ def test_batch_u8_run_and_graph_bit_exact():
     plan.close()
 
 
-def test_batch_autotune_keeps_results(tmp_path):
+@pytest.mark.parametrize("fill", FILLS)
+def test_batch_autotune_keeps_results(tmp_path, fill):
     st = _streams(MIX[:4], seed=3)
     cache = str(tmp_path / "tune.txt")
     plan = aol.BatchPlan([(h, w, hf, vf) for (h, w, hf, vf, _, _) in st], "u8", tune_cache=cache)
     frames = _frames(MIX[:4], 1, 11)
     ins = [torch.from_numpy(fs[0]).cuda() for fs in frames]
-    outs = [torch.empty(plan.out_shapes[i], dtype=torch.uint8, device="cuda") for i in range(len(st))]
+    outs = [torch.full(plan.out_shapes[i], fill, dtype=torch.uint8, device="cuda") for i in range(len(st))]
     plan.set_pointers(ins, outs)
     plan.autotune()
     sched = plan.schedule()
@@ -116,7 +121,8 @@ def test_batch_float_within_tolerance(fmt):
     plan.close()
 
 
-def test_batch_64_streams_mix_one_step():
+@pytest.mark.parametrize("fill", FILLS)
+def test_batch_64_streams_mix_one_step(fill):
     """The 64-stream mix (sizes 640x480..3840x2160, ratios 3/8, 1/2, 2/3, 8..16 taps): one step, all outputs."""
     mix = synthgen.stream_mix(2011, 64)
     filt = {}
@@ -131,7 +137,7 @@ def test_batch_64_streams_mix_one_step():
     g = synthgen.rng_for(2011, 9)
     frames = [synthgen.gradient_plane(g, s.h, s.w) for s in mix]
     ins = [torch.from_numpy(f).cuda() for f in frames]
-    outs = [torch.empty(plan.out_shapes[i], dtype=torch.uint8, device="cuda") for i in range(len(mix))]
+    outs = [torch.full(plan.out_shapes[i], fill, dtype=torch.uint8, device="cuda") for i in range(len(mix))]
     plan.set_pointers(ins, outs)
     plan.run()
     torch.cuda.synchronize()
@@ -141,7 +147,8 @@ def test_batch_64_streams_mix_one_step():
     plan.close()
 
 
-def test_batch_int8_taps_streams_of_the_mix():
+@pytest.mark.parametrize("fill", FILLS)
+def test_batch_int8_taps_streams_of_the_mix(fill):
     """The streams of the 64-stream mix whose filters fit int8 taps: the fast kernel instance with
     several filters, sizes and K-step counts in one launch, several units per workgroup."""
     mix = [s for s in synthgen.stream_mix(2011, 64)
@@ -159,11 +166,90 @@ def test_batch_int8_taps_streams_of_the_mix():
     g = synthgen.rng_for(2011, 10)
     frames = [synthgen.gradient_plane(g, s.h, s.w) for s in mix]
     ins = [torch.from_numpy(f).cuda() for f in frames]
-    outs = [torch.empty(plan.out_shapes[i], dtype=torch.uint8, device="cuda") for i in range(len(mix))]
+    outs = [torch.full(plan.out_shapes[i], fill, dtype=torch.uint8, device="cuda") for i in range(len(mix))]
     plan.set_pointers(ins, outs)
     plan.run()
     torch.cuda.synchronize()
     for i, s in enumerate(mix):
         of = filt[(s.p, s.q, s.taps)][1]
         np.testing.assert_array_equal(outs[i].cpu().numpy(), pp.downscale_u8(frames[i], of, of), err_msg=f"stream {i}")
+    plan.close()
+
+
+def _mix64():
+    mix = synthgen.stream_mix(2011, 64)
+    filt = {}
+    streams = []
+    for s in mix:
+        key = (s.p, s.q, s.taps)
+        if key not in filt:
+            c = synthgen.design_taps(s.p, s.q, s.taps)
+            filt[key] = (aol.Polyphase(s.p, s.q, c), pp.Filter(s.p, s.q, c))
+        streams.append((s.h, s.w, filt[key][0], filt[key][0]))
+    return mix, filt, streams
+
+
+# the schedules the autotuner times: segment lengths x LDS budgets (column bands)
+TUNE_SEGS = (16, 32, 64, 128)
+TUNE_BUDGETS = (150 * 1024, 76 * 1024)
+
+
+def test_batch_every_tuner_candidate_identical():
+    """The 64-stream mix under every schedule the autotuner may pick: each candidate's outputs
+    equal the first candidate's on all 64 streams, and the first equals the oracle (results do
+    not depend on the schedule)."""
+    mix, filt, streams = _mix64()
+    plan = aol.BatchPlan(streams, "u8")
+    g = synthgen.rng_for(2011, 12)
+    frames = [synthgen.gradient_plane(g, s.h, s.w) for s in mix]
+    ins = [torch.from_numpy(f).cuda() for f in frames]
+    first = None
+    n_cand = 0
+    for budget in TUNE_BUDGETS:
+        for seg in TUNE_SEGS:
+            try:
+                plan.set_schedule(seg, budget)
+            except aol.AolError as e:
+                assert e.status == aol.AOL_ERR_UNSUPPORTED, e.msg
+                continue
+            n_cand += 1
+            outs = [torch.full(plan.out_shapes[i], 0xFF if n_cand % 2 else 0x00, dtype=torch.uint8, device="cuda")
+                    for i in range(len(mix))]
+            plan.set_pointers(ins, outs)
+            plan.run()
+            torch.cuda.synchronize()
+            if first is None:
+                first = outs
+                for i, s in enumerate(mix):
+                    of = filt[(s.p, s.q, s.taps)][1]
+                    np.testing.assert_array_equal(outs[i].cpu().numpy(), pp.downscale_u8(frames[i], of, of),
+                                                  err_msg=f"stream {i}")
+            else:
+                for i in range(len(mix)):
+                    assert torch.equal(outs[i], first[i]), f"seg {seg} budget {budget}: stream {i} differs"
+    assert n_cand >= 4
+    plan.close()
+
+
+def test_batch_graph_refused_after_reschedule():
+    """A graph captured before the schedule changes is refused instead of running its old launch
+    over the new tables; a graph captured afterwards runs."""
+    st = _streams(MIX[:3])
+    plan = aol.BatchPlan([(h, w, hf, vf) for (h, w, hf, vf, _, _) in st], "u8")
+    frames = _frames(MIX[:3], 1, 21)
+    ins = [torch.from_numpy(fs[0]).cuda() for fs in frames]
+    outs = [torch.full(plan.out_shapes[i], 0, dtype=torch.uint8, device="cuda") for i in range(len(st))]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.set_pointers(ins, outs, s)
+        g_old = plan.graph(s)
+        plan.set_schedule(32, 76 * 1024)
+        with pytest.raises(aol.AolError) as ei:
+            aol.aol_graph_launch(g_old, s)
+        assert ei.value.status == aol.AOL_ERR_INVALID
+        g_new = plan.graph(s)
+        aol.aol_graph_launch(g_new, s)
+    s.synchronize()
+    for i, (h, w, hf, vf, of, ov) in enumerate(st):
+        np.testing.assert_array_equal(outs[i].cpu().numpy(), pp.downscale_u8(frames[i][0], of, ov))
     plan.close()

@@ -12,10 +12,11 @@ import pytest
 import synthgen
 from oracle import polyphase as pp
 
-torch = pytest.importorskip("torch")
-pytestmark = pytest.mark.gpu
+import torch
 
-aol = pytest.importorskip("paper_1103_4881_amd")
+import paper_1103_4881_amd as aol  # a missing library fails the suite (no skip)
+
+pytestmark = pytest.mark.gpu
 
 FLOAT_TOL = 1e-3
 
@@ -35,33 +36,43 @@ def _filters(p, q, T, kind="design", seed=0, starts=None):
     return aol.Polyphase(p, q, c, starts), pp.Filter(p, q, c, starts)
 
 
+FILLS = (0x00, 0xFF)  # output sentinels: an element left unwritten differs between the two runs
+
+
 def _run_u8(planes_np, hf, vf, tile=None, in_pitch_pad=0, out_pitch_pad=0):
-    """planes_np: list of uint8 arrays [F, H, W]. Returns list of uint8 [F, MH, MW]."""
+    """planes_np: list of uint8 arrays [F, H, W]. Runs the plan once per sentinel fill of the
+    outputs (0x00, then 0xFF), requires both runs to agree on every output element (so every
+    element was written) and to leave the row padding alone; returns uint8 [F, MH, MW] per plane."""
     shapes = [a.shape[1:] for a in planes_np]
     out_shapes = [aol.aol_downscale_output_shape(h, w, hf, vf) for (h, w) in shapes]
-    ins, outs, ip, op = [], [], [], []
+    ins, ip, op = [], [], []
     for a, (oh, ow) in zip(planes_np, out_shapes):
         F, H, W = a.shape
         buf = torch.full((F, H, W + in_pitch_pad), 77, dtype=torch.uint8, device="cuda")
         buf[:, :, :W] = torch.from_numpy(a).cuda()
         ins.append(buf[:, :, :W])
         ip.append(W + in_pitch_pad)
-        ob = torch.full((F, oh, ow + out_pitch_pad), 0xA5, dtype=torch.uint8, device="cuda")
-        outs.append(ob)
         op.append(ow + out_pitch_pad)
     plan = aol.DownscalePlan(shapes, hf, vf, "u8", in_pitches=ip, out_pitches=op)
     if tile:
         plan.set_tile(*tile)
-    plan.run(ins, [o[:, :, :s[1]] for o, s in zip(outs, out_shapes)])
-    torch.cuda.synchronize()
-    res = []
-    for o, (oh, ow) in zip(outs, out_shapes):
-        o = o.cpu().numpy()
-        if out_pitch_pad:
-            assert (o[:, :, ow:] == 0xA5).all(), "write outside the output rows"
-        res.append(o[:, :, :ow])
+    runs = []
+    for fill in FILLS:
+        outs = [torch.full((a.shape[0], oh, ow + out_pitch_pad), fill, dtype=torch.uint8, device="cuda")
+                for a, (oh, ow) in zip(planes_np, out_shapes)]
+        plan.run(ins, [o[:, :, :s[1]] for o, s in zip(outs, out_shapes)])
+        torch.cuda.synchronize()
+        res = []
+        for o, (oh, ow) in zip(outs, out_shapes):
+            o = o.cpu().numpy()
+            if out_pitch_pad:
+                assert (o[:, :, ow:] == fill).all(), "write outside the output rows"
+            res.append(o[:, :, :ow])
+        runs.append(res)
+    for a, b in zip(*runs):
+        np.testing.assert_array_equal(a, b, err_msg="outputs differ between sentinel fills (unwritten elements)")
     plan.close()
-    return res
+    return runs[0]
 
 
 def test_config1_vga_frame_bit_exact():
@@ -155,16 +166,78 @@ def test_i420_frames_every_tile_shape_identical():
             np.testing.assert_array_equal(g, r)
 
 
-def test_1080p_i420_bench_launch_sampled_frames():
-    """The benchmark's launch: I420 1080p frames in one launch; every output of several frames checked."""
+def test_1080p_i420_six_frames_every_frame():
+    """Six I420 1080p frames in one launch (short segments: few frames); every output of
+    every frame checked."""
     n = 6
     Yp, Up, Vp = synthgen.yuv420_frames(11, n, 1080, 1920)
     hf, of = _filters(3, 8, 11)
     got = _run_u8([Yp, Up, Vp], hf, hf)
     assert got[0].shape == (n, 405, 720) and got[1].shape == (n, 204, 360)
-    for f in (0, n // 2, n - 1):
+    for f in range(n):
         for g, a in zip(got, (Yp, Up, Vp)):
-            np.testing.assert_array_equal(g[f], pp.downscale_u8(a[f], of, of))
+            np.testing.assert_array_equal(g[f], pp.downscale_u8(a[f], of, of), err_msg=f"frame {f}")
+
+
+# The benchmark's workload: 300 I420 1080p frames (seed, filter and plan as in bench.py)
+BENCH_SEED, BENCH_FRAMES = 20110322, 300
+
+
+def test_headline_launch_300_frames():
+    """The launch bench.py times: 300 I420 1920x1080 frames, 3/8 with 11 taps on both axes, the
+    automatic schedule (segments of up to 64 repetitions: 7 units per frame, 2100 items dealt over
+    the workgroups). Runs twice, outputs pre-filled with 0x00 and with 0xFF: the two runs agree on
+    all 300 frames (every output written); sampled frames equal the oracle on every element."""
+    n = BENCH_FRAMES
+    Yp, Up, Vp = synthgen.yuv420_frames(BENCH_SEED, n, 1080, 1920)
+    c = synthgen.design_taps(3, 8, 11)
+    f = aol.Polyphase(3, 8, c)
+    of = pp.Filter(3, 8, c)
+    plan = aol.DownscalePlan([(1080, 1920), (540, 960), (540, 960)], f, f, "u8")
+    sched = plan.schedule(n)
+    assert sched["kernel"] == "band" and sched["seg"] == 64 and sched["units_per_frame"] == 7, sched
+    assert sched["items"] == 7 * n and sched["split"] == 0 and sched["kmax"] == 1, sched
+    ins = [torch.from_numpy(a).cuda() for a in (Yp, Up, Vp)]
+    runs = []
+    for fill in FILLS:
+        outs = [torch.full((n,) + s, fill, dtype=torch.uint8, device="cuda") for s in plan.out_shapes]
+        plan.run(ins, outs)
+        torch.cuda.synchronize()
+        runs.append(outs)
+    for j, (a, b) in enumerate(zip(*runs)):
+        assert torch.equal(a, b), f"plane {j}: outputs differ between sentinel fills"
+    g = synthgen.rng_for(BENCH_SEED, 77)
+    frames = sorted({0, 1, n // 2 - 1, n // 2, n - 2, n - 1, *g.integers(0, n, size=4).tolist()})
+    for fr in frames:
+        for j, (o, a) in enumerate(zip(runs[0], (Yp, Up, Vp))):
+            np.testing.assert_array_equal(o[fr].cpu().numpy(), pp.downscale_u8(a[fr], of, of),
+                                          err_msg=f"frame {fr} plane {j}")
+    plan.close()
+
+
+def test_first_run_captured_in_a_graph():
+    """A plan's very first run, captured in a graph and replayed: run calls only enqueue (no
+    allocation, copy or synchronisation), so the capture holds the whole launch."""
+    Yp, Up, Vp = synthgen.yuv420_frames(19, 3, 270, 480)
+    hf, of = _filters(3, 8, 11)
+    plan = aol.DownscalePlan([a.shape[1:] for a in (Yp, Up, Vp)], hf, hf, "u8")
+    ins = [torch.from_numpy(a).cuda() for a in (Yp, Up, Vp)]
+    outs = [torch.full((3,) + s, 0xA5, dtype=torch.uint8, device="cuda") for s in plan.out_shapes]
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.run(ins, outs)
+    refs = [pp.downscale_u8(a, of, of) for a in (Yp, Up, Vp)]
+    for rep, fill in enumerate((0x00, 0xFF, 0x00)):
+        for o in outs:
+            o.fill_(fill)  # eager work between the replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for j, (o, r) in enumerate(zip(outs, refs)):
+            np.testing.assert_array_equal(o.cpu().numpy(), r, err_msg=f"replay {rep} plane {j}")
+    del graph
+    plan.close()
 
 
 @pytest.mark.parametrize("fmt", ["u8", "bf16"])
@@ -248,11 +321,12 @@ def test_band_schedules_bit_exact(band, seg):
     plan = aol.DownscalePlan(shapes, hf, vf, "u8")
     plan.set_band(band, seg)
     ins = [torch.from_numpy(a).cuda() for a in (Yp, Up, Vp)]
-    outs = [torch.full((2,) + s, 0xA5, dtype=torch.uint8, device="cuda") for s in plan.out_shapes]
-    plan.run(ins, outs)
-    torch.cuda.synchronize()
-    for o, a in zip(outs, (Yp, Up, Vp)):
-        np.testing.assert_array_equal(o.cpu().numpy(), pp.downscale_u8(a, of, ov))
+    for fill in FILLS:
+        outs = [torch.full((2,) + s, fill, dtype=torch.uint8, device="cuda") for s in plan.out_shapes]
+        plan.run(ins, outs)
+        torch.cuda.synchronize()
+        for o, a in zip(outs, (Yp, Up, Vp)):
+            np.testing.assert_array_equal(o.cpu().numpy(), pp.downscale_u8(a, of, ov), err_msg=f"fill {fill}")
     plan.close()
 
 

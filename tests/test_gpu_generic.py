@@ -9,9 +9,11 @@ import synthgen
 from oracle import generic as gn
 from oracle.arrayol import Tiler
 
-torch = pytest.importorskip("torch")
+import torch
+
+import paper_1103_4881_amd as aol  # a missing library fails the suite (no skip)
+
 pytestmark = pytest.mark.gpu
-aol = pytest.importorskip("paper_1103_4881_amd")
 
 REL = 1e-5
 
@@ -106,3 +108,22 @@ def test_full_size_64x1024x1024_sampled():
     ref, mag = gn.weighted_sum_at(A, _otiler(rt), w, r)
     _check(yc[tuple(r)], ref, mag)
     plan.close()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_one_shot_entry_point_equals_plan(seed):
+    """aol_weighted_sum_f32 (no plan, weights in the kernel arguments) writes the same bits as a
+    plan's run, and equals the oracle."""
+    rt = synthgen.random_tiler(40 + seed, array_shape=(24, 40, 36), pat_shape=(5, 5))
+    A = synthgen.rng_for(40 + seed, 1).uniform(-1, 1, size=rt.array_shape).astype(np.float32)
+    w = synthgen.rng_for(40 + seed, 2).uniform(-1, 1, size=(5, 5)).astype(np.float32)
+    tin, tout = _atiler(rt), aol.identity_out_tiler(rt.rep_shape)
+    via_plan = _run(A, tin, tout, w)
+    x = torch.from_numpy(A).cuda()
+    y = torch.full(tuple(rt.rep_shape), float("nan"), dtype=torch.float32, device="cuda")
+    aol.aol_weighted_sum_f32(tin, tout, w, x.data_ptr(), y.data_ptr())
+    torch.cuda.synchronize()
+    got = y.cpu().numpy()
+    np.testing.assert_array_equal(got, via_plan)
+    B, M, _ = gn.weighted_sum_f64(A, _otiler(rt), w, _otiler_id(rt.rep_shape), rt.rep_shape)
+    _check(got, B, M)
