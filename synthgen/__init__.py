@@ -243,3 +243,82 @@ def random_tiler(seed: int, array_shape=(64, 1024, 1024), pat_shape=(5, 5), idx:
     origin = tuple(int(g.integers(0, S[a])) for a in range(d))
     R = tuple(int(-(-S[perm[k]] // int(strides[k]))) for k in range(d))
     return RandomTiler(S, R, tuple(int(v) for v in pat_shape), origin, P, F)
+
+
+# --------------------------------------------------------------------------
+# linear integer tasks: tiler specifications and caller weights
+# --------------------------------------------------------------------------
+
+@dataclass
+class TilerSpec:
+    array_shape: tuple
+    origin: tuple
+    paving: list      # [array dim][rep dim]
+    fitting: list     # [array dim][pattern dim]
+    pat_shape: tuple
+
+
+def rgb_to_planar_tilers(h: int, w: int):
+    """Interleaved RGB [h, 3w] to planar [3, h, w]: repetition space (h, w); the input pattern is
+    the three adjacent bytes of a pixel (paving 3 along the row, fitting 1), the output pattern
+    one byte in each plane. Returns (rep_shape, tin, tout)."""
+    tin = TilerSpec((h, 3 * w), (0, 0), [[1, 0], [0, 3]], [[0], [1]], (3,))
+    tout = TilerSpec((3, h, w), (0, 0, 0), [[0, 0], [1, 0], [0, 1]], [[1], [0], [0]], (3,))
+    return (h, w), tin, tout
+
+
+def planar_to_rgb_tilers(h: int, w: int):
+    """Planar [3, h, w] back to interleaved RGB [h, 3w] (the composition of the frame)."""
+    tin = TilerSpec((3, h, w), (0, 0, 0), [[0, 0], [1, 0], [0, 1]], [[1], [0], [0]], (3,))
+    tout = TilerSpec((h, 3 * w), (0, 0), [[1, 0], [0, 3]], [[0], [1]], (3,))
+    return (h, w), tin, tout
+
+
+# Caller weights of the colour conversions, scaled by 256 (full-range BT.601
+# approximations; rows of the RGB->YCbCr matrix sum to 256 for luma and 0 for
+# chroma, the chroma offset 128 is the bias 128*256).
+RGB_TO_YCC_W = np.array([[77, 150, 29], [-43, -85, 128], [128, -107, -21]], np.int16)
+RGB_TO_YCC_BIAS = np.array([0, 128 * 256, 128 * 256], np.int32)
+YCC_TO_RGB_W = np.array([[256, 0, 359], [256, -88, -183], [256, 454, 0]], np.int16)
+YCC_TO_RGB_BIAS = np.array([-359 * 128, (88 + 183) * 128, -454 * 128], np.int32)
+
+
+def polyphase2d_tilers(h: int, w: int, p: int, q: int, taps: int):
+    """Non-separable 2-D polyphase filter as one repetition per q x q packet: the input
+    pattern is the union window (span x span) of the p phases along each axis, the output
+    pattern the p x p outputs of the packet. Window starts: the default pixel-centre
+    placement. Returns (rep_shape, tin, tout, starts, span)."""
+    starts = [((2 * phi + 1) * q - p) // (2 * p) - (taps - 1) // 2 for phi in range(p)]
+    lo = min(starts)
+    span = max(s + taps for s in starts) - lo
+    ry, rx = -(-h // q), -(-w // q)
+    tin = TilerSpec((h, w), (lo, lo), [[q, 0], [0, q]], [[1, 0], [0, 1]], (span, span))
+    tout = TilerSpec((p * ry, p * rx), (0, 0), [[p, 0], [0, p]], [[1, 0], [0, 1]], (p, p))
+    return (ry, rx), tin, tout, starts, span
+
+
+def polyphase2d_weights(seed: int, p: int, q: int, taps: int):
+    """Caller weights W[p*p][span*span] of a non-separable 2-D polyphase filter: for output
+    phase (py, px) a taps x taps kernel (the outer product of the 1-D design plus a seeded
+    random non-separable part, rounded so each kernel sums to 256) placed in the union window."""
+    _, _, _, starts, span = polyphase2d_tilers(q, q, p, q, taps)
+    lo = min(starts)
+    c = design_taps(p, q, taps).astype(np.float64) / 256.0
+    g = rng_for(seed, 7)
+    W = np.zeros((p * p, span * span), np.int64)
+    for py in range(p):
+        for px in range(p):
+            k = np.outer(c[py], c[px]) + 0.02 * g.standard_normal((taps, taps))
+            k = 256.0 * k / k.sum()
+            base = np.floor(k)
+            rem = (k - base).ravel()
+            ki = base.astype(np.int64).ravel()
+            order = sorted(range(ki.size), key=lambda t: (-rem[t], t))
+            for t in range(256 - int(ki.sum())):
+                ki[order[t % ki.size]] += 1
+            ki = ki.reshape(taps, taps)
+            oy, ox = starts[py] - lo, starts[px] - lo
+            full = np.zeros((span, span), np.int64)
+            full[oy:oy + taps, ox:ox + taps] = ki
+            W[py * p + px] = full.ravel()
+    return W.astype(np.int16)
