@@ -169,6 +169,87 @@ def bench_u8(Yh, Uh, Vh, steps, warmup):
                 mismatches=mism, checked_elements=checked, checked_frames=check_frames(n))
 
 
+def bench_unfused(u8, Yh, Uh, Vh, steps, warmup):
+    """The unfused form (a horizontal and a vertical row-pass kernel, the uint8 intermediate
+    through HBM) on the same frames and plan, with a workspace for all frames (one launch per
+    pass): outputs identical to the fused launch's, and the time and bytes fusion saves."""
+    import torch
+    plan = u8["plan"]
+    ins = u8["ins"]
+    n = ins[0].shape[0]
+    work = torch.empty(plan.workspace_bytes() * n, dtype=torch.uint8, device="cuda")
+    outs = [torch.empty((n,) + s, dtype=torch.uint8, device="cuda") for s in plan.out_shapes]
+    stream = torch.cuda.current_stream()
+    ms_step, ms_kernel, ms_med = time_launches(lambda: plan.run_unfused(ins, outs, work), steps, warmup, stream)
+    same = all(torch.equal(a, b) for a, b in zip(outs, u8["outs"]))
+    # bytes: the fused launch's, plus the intermediate written once and read once
+    ch, cw = H // 2, W // 2
+    z = H * (P * -(-W // Q)) + 2 * ch * (P * -(-cw // Q))
+    bytes_unf = u8["bytes"] + 2 * z * n
+    del work, outs
+    torch.cuda.empty_cache()
+    gbs = bytes_unf / (ms_kernel / 1e3) / 1e9
+    return {"ms_per_step": round(ms_step, 4), "ms_two_passes_mean": round(ms_kernel, 4),
+            "ms_two_passes_median": round(ms_med, 4), "identical_to_fused": bool(same),
+            "bytes_per_step": bytes_unf, "intermediate_bytes": 2 * z * n,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4)},
+            "fusion_gain": {"time": round(ms_step / u8["ms_step"], 3),
+                            "bytes": round(bytes_unf / u8["bytes"], 3)}}
+
+
+CIF_FRAMES = 2000
+
+
+def bench_cif(n=CIF_FRAMES):
+    """The paper's own workload: I420 CIF frames (352x288 luma), 3/8 along lines and 4/9 along
+    columns (-> 132x128), frames in host memory. The host-to-host pipeline in four forms: one
+    frame at a time with no overlap (pageable, then pinned host memory), one frame at a time with
+    four frames in flight, and groups of 50 frames with three groups in flight (pinned). Stage
+    times are sums of per-group GPU events; `transfer_share` is the copies' part of the stage
+    time, `overlap` the stage time over the span from the first copy to the last."""
+    import torch
+    import paper_1103_4881_amd as aol
+    import synthgen
+    from oracle import polyphase as pp
+    planes = synthgen.yuv420_frames(SEED + 1, n, 288, 352)
+    ch, cv = synthgen.design_taps(3, 8, 11), synthgen.design_taps(4, 9, 11)
+    plan = aol.DownscalePlan([(288, 352), (144, 176), (144, 176)], aol.Polyphase(3, 8, ch),
+                             aol.Polyphase(4, 9, cv), "u8")
+    pinned_in = [torch.from_numpy(a).pin_memory() for a in planes]
+    pageable_in = [torch.from_numpy(a) for a in planes]
+    res = {"frames": n, "in": "352x288 I420", "out": "132x128 I420", "h": "3/8, 11 taps", "v": "4/9, 11 taps",
+           "bytes_in": n * (288 * 352 + 2 * 144 * 176), "bytes_out": n * (128 * 132 + 2 * 64 * 66), "forms": {}}
+    of, ov = pp.Filter(3, 8, ch), pp.Filter(4, 9, cv)
+    mism = 0
+    for name, batch, depth, pinned in [("per_frame_serial_pageable", 1, 1, False), ("per_frame_serial", 1, 1, True),
+                                       ("per_frame_overlapped", 1, 4, True), ("groups_of_50", 50, 3, True)]:
+        ins = pinned_in if pinned else pageable_in
+        outs = [torch.empty((n,) + s, dtype=torch.uint8, pin_memory=pinned) for s in plan.out_shapes]
+        pipe = aol.Pipeline(plan, batch, depth)
+        pipe.run([t[:2 * batch] for t in ins], [o[:2 * batch] for o in outs])  # warm-up
+        st = pipe.run(ins, outs)
+        pipe.close()
+        for fr in check_frames(n):
+            for o, a in zip(outs, planes):
+                mism += int((o[fr].numpy() != pp.downscale_u8(a[fr], of, ov)).sum())
+        stage = st["h2d_ms"] + st["kernel_ms"] + st["d2h_ms"]
+        res["forms"][name] = {
+            "batch_frames": batch, "depth": depth, "host_memory": "pinned" if pinned else "pageable",
+            "wall_ms": round(st["wall_ms"], 2), "span_ms": round(st["span_ms"], 2),
+            "h2d_ms": round(st["h2d_ms"], 2), "kernel_ms": round(st["kernel_ms"], 2), "d2h_ms": round(st["d2h_ms"], 2),
+            "transfer_share": round((st["h2d_ms"] + st["d2h_ms"]) / stage, 3),
+            "overlap": round(stage / st["span_ms"], 3) if st["span_ms"] > 0 else None,
+            "frames_per_s": round(n / (st["wall_ms"] / 1e3), 1),
+            "h2d_gbs": round(st["h2d_bytes"] / (st["h2d_ms"] / 1e3) / 1e9, 2),
+            "d2h_gbs": round(st["d2h_bytes"] / (st["d2h_ms"] / 1e3) / 1e9, 2)}
+        log(f"cif {name}: {st['wall_ms']:.1f} ms wall, h2d {st['h2d_ms']:.1f} kernel {st['kernel_ms']:.1f} "
+            f"d2h {st['d2h_ms']:.1f} ms")
+    res["mismatches_sampled_frames"] = mism
+    plan.close()
+    return res
+
+
 def bench_config1(reps=100, warmup=200):
     """One 640x480 uniform random frame -> 180x240 (3/8, 11 taps): launch latency. The 350 KB
     working set stays in the caches, so this is a latency figure, not an HBM measurement."""
@@ -468,6 +549,7 @@ def cpu_baseline(n_frames, repeats, single_frames):
 # ------------------------------------------------------------------ main
 
 def main():
+    global WARM_SECONDS
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
@@ -478,14 +560,17 @@ def main():
     ap.add_argument("--cpu-single-frames", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-float", action="store_true")
-    ap.add_argument("--only", choices=["u8", "bf16", "fp16", "batch", "generic", "config1"], default=None,
+    ap.add_argument("--only", choices=["u8", "unfused", "bf16", "fp16", "batch", "generic", "config1", "cif"], default=None,
                     help="run one workload only (for profiling)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-generic", action="store_true")
+    ap.add_argument("--warm-seconds", type=float, default=WARM_SECONDS,
+                    help="extra warm-up time before each timed region (0 under a counter profiler)")
     ap.add_argument("--hash", action="store_true", help="print the fused kernel's source hash and exit")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 3 times (scale for HBM byte counters)")
     args = ap.parse_args()
+    WARM_SECONDS = args.warm_seconds
     if args.hash:
         print(kernel_hash())
         return
@@ -516,6 +601,11 @@ def main():
     if args.only is None:
         extra["copy_peak_gbs"] = round(copy_peak(), 1)
         log(f"copy: {extra['copy_peak_gbs']} GB/s")
+    if args.only in (None, "cif"):
+        extra["paper_cif_pipeline"] = bench_cif()
+        if args.only:
+            print(json.dumps({"metric": METRIC, **extra}), flush=True)
+            return
     if args.only in (None, "config1"):
         extra["config1"] = bench_config1()
         log(f"config1: {extra['config1']['us_median']} us")
@@ -527,10 +617,14 @@ def main():
     log(f"generated {args.frames} I420 frames in {time.time() - t:.1f} s")
 
     u8 = None
-    if args.only in (None, "u8"):
+    if args.only in (None, "u8", "unfused"):
         u8 = bench_u8(Yh, Uh, Vh, args.steps, args.warmup)
         log(f"u8 fused: {u8['ms_step']:.3f} ms/step, kernel {u8['ms_kernel']:.3f} ms, "
             f"mismatches {u8['mismatches']}")
+    if u8 and args.only in (None, "unfused"):
+        extra["unfused_u8"] = bench_unfused(u8, Yh, Uh, Vh, args.steps, args.warmup)
+        log(f"unfused u8: {extra['unfused_u8']['ms_per_step']:.3f} ms/step, identical "
+            f"{extra['unfused_u8']['identical_to_fused']}")
     fl = {}
     if not args.no_float and args.only in (None, "bf16", "fp16"):
         ins_u8 = u8["ins"] if u8 else [torch.from_numpy(a).cuda() for a in (Yh, Uh, Vh)]

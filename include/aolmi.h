@@ -184,6 +184,79 @@ aol_status aol_downscale_f(aol_plan* plan, int32_t n_frames, const void* const* 
                            const int64_t* out_frame_stride, hipStream_t stream);
 
 /* --------------------------------------------------------------------------
+ * Unfused form of an integer plan (Sec. III-A: the horizontal and the
+ * vertical filter are separate repetitive tasks connected by the
+ * intermediate frame array). Two kernels per group of frames: the first
+ * filters every line and writes the uint8 intermediate, transposed, into a
+ * caller-supplied device workspace; the second filters every row of that
+ * (i.e. every column of the intermediate) and writes the outputs. Results
+ * are identical to aol_downscale_u8, bit for bit; the intermediate makes one
+ * round trip through memory, which the fused kernel avoids.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes one frame of the plan's planes needs (its transposed
+ * intermediates, rows padded to 128 bytes). AOL_ERR_INVALID for a float
+ * plan, AOL_ERR_UNSUPPORTED for filters whose 16-output blocks span more
+ * than four K-steps of 64 pixels. */
+aol_status aol_unfused_workspace_bytes(aol_plan* plan, int64_t* bytes_per_frame);
+
+/* Arguments as aol_downscale_u8, plus d_work: device memory of work_bytes
+ * bytes, 256-byte aligned, owned by the caller, not aliasing any input or
+ * output. Frames run in groups of floor(work_bytes / bytes_per_frame), in
+ * order, on stream (AOL_ERR_INVALID if the workspace holds no frame). The
+ * workspace's contents are scratch: the caller must not use it while the
+ * call's work is in flight. Enqueue only; vector loads need 16-byte aligned
+ * input rows, other layouts take a byte-wise path. */
+aol_status aol_downscale_u8_unfused(aol_plan* plan, int32_t n_frames, const uint8_t* const* d_in,
+                                    const int64_t* in_frame_stride, uint8_t* const* d_out,
+                                    const int64_t* out_frame_stride, void* d_work, int64_t work_bytes,
+                                    hipStream_t stream);
+
+/* --------------------------------------------------------------------------
+ * Host-to-host frame pipeline (Sec. IV: in the paper's measurements the
+ * copies between host and device memory take most of the application's
+ * time, and its tuning removes redundant ones). Frames live in host memory;
+ * groups of batch_frames frames are copied to the device on one stream,
+ * downscaled by the plan's fused kernel on the caller's stream and copied
+ * back on another stream, with `depth` groups in flight in a ring of device
+ * slots, so the copies of one group overlap the kernel of another. Host
+ * buffers should be pinned (hipHostMalloc, or torch's pin_memory=True) for
+ * the copies to run asynchronously; pageable memory works but its copies
+ * are staged by the runtime.
+ * ------------------------------------------------------------------------ */
+typedef struct aol_pipeline aol_pipeline;
+
+typedef struct aol_pipeline_stats {
+  int32_t groups;     /* groups of frames moved */
+  int32_t frames;
+  double wall_ms;     /* host time of the call */
+  double span_ms;     /* first host-to-device copy start to last device-to-host copy end (GPU clock) */
+  double h2d_ms;      /* sums over the groups of each stage's duration (GPU clock) */
+  double kernel_ms;
+  double d2h_ms;
+  int64_t h2d_bytes;  /* bytes copied each way */
+  int64_t d2h_bytes;
+} aol_pipeline_stats;
+
+/* Allocates the device slots (depth x batch_frames frames of every plane of
+ * an integer plan, in and out) and two copy streams of the default
+ * priority. The plan must outlive the pipeline. AOL_ERR_INVALID for a float
+ * plan, batch_frames < 1 or depth outside 1..64. */
+aol_status aol_pipeline_create(aol_plan* plan, int32_t batch_frames, int32_t depth, aol_pipeline** out);
+aol_status aol_pipeline_destroy(aol_pipeline* pipe);
+
+/* h_in[j] / h_out[j]: host memory of frame 0 of plane j, frames
+ * in_frame_stride[j] / out_frame_stride[j] bytes apart, rows at the plan's
+ * pitches. Outputs are bit-identical to aol_downscale_u8. Not a run call: it
+ * enqueues the three stages group by group, waits on the host before reusing
+ * a slot, and returns once every output is in host memory. stats may be
+ * NULL. One call at a time per pipeline. With n_frames 0 the buffers are not
+ * read and may be NULL. */
+aol_status aol_pipeline_run_u8(aol_pipeline* pipe, int32_t n_frames, const uint8_t* const* h_in,
+                               const int64_t* in_frame_stride, uint8_t* const* h_out,
+                               const int64_t* out_frame_stride, hipStream_t stream, aol_pipeline_stats* stats);
+
+/* --------------------------------------------------------------------------
  * Batches of video streams (Sec. III: the downscaler repeats for every frame;
  * Sec. III-A: all elementary tasks are independent, so frames of different
  * streams may run together). One step downscales one frame of every stream,

@@ -92,6 +92,23 @@ _proto("aol_downscale_u8", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes
 _proto("aol_downscale_f", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), c_i64p,
        ctypes.POINTER(ctypes.c_void_p), c_i64p, ctypes.c_void_p)
 
+_proto("aol_unfused_workspace_bytes", ctypes.c_int, ctypes.c_void_p, c_i64p)
+_proto("aol_downscale_u8_unfused", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), c_i64p,
+       ctypes.POINTER(ctypes.c_void_p), c_i64p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p)
+
+
+class aol_pipeline_stats(ctypes.Structure):
+    _fields_ = [("groups", ctypes.c_int32), ("frames", ctypes.c_int32), ("wall_ms", ctypes.c_double),
+                ("span_ms", ctypes.c_double), ("h2d_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("d2h_ms", ctypes.c_double), ("h2d_bytes", ctypes.c_int64), ("d2h_bytes", ctypes.c_int64)]
+
+
+_proto("aol_pipeline_create", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+       ctypes.POINTER(ctypes.c_void_p))
+_proto("aol_pipeline_destroy", ctypes.c_int, ctypes.c_void_p)
+_proto("aol_pipeline_run_u8", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), c_i64p,
+       ctypes.POINTER(ctypes.c_void_p), c_i64p, ctypes.c_void_p, ctypes.POINTER(aol_pipeline_stats))
+
 
 class aol_stream_desc(ctypes.Structure):
     _fields_ = [("height", ctypes.c_int64), ("width", ctypes.c_int64), ("in_pitch", ctypes.c_int64),
@@ -237,6 +254,19 @@ def aol_downscale_f(plan, n_frames, d_in, in_frame_stride, d_out, out_frame_stri
                                 _i64s(out_frame_stride), _stream_handle(stream)))
 
 
+def aol_unfused_workspace_bytes(plan) -> int:
+    n = ctypes.c_int64()
+    _check(_lib.aol_unfused_workspace_bytes(plan, ctypes.byref(n)))
+    return n.value
+
+
+def aol_downscale_u8_unfused(plan, n_frames, d_in, in_frame_stride, d_out, out_frame_stride, d_work, work_bytes,
+                             stream=None):
+    _check(_lib.aol_downscale_u8_unfused(plan, int(n_frames), _ptrs(d_in), _i64s(in_frame_stride), _ptrs(d_out),
+                                         _i64s(out_frame_stride), ctypes.c_void_p(int(d_work)), int(work_bytes),
+                                         _stream_handle(stream)))
+
+
 class DownscalePlan:
     """Plan for a set of planes filtered by (hf, vf); runs on torch device tensors.
 
@@ -303,11 +333,84 @@ class DownscalePlan:
                     raise ValueError("float plans take 16-bit inputs and float32 outputs")
         return n
 
+    def workspace_bytes(self) -> int:
+        """Workspace bytes per frame of the unfused form (integer plans)."""
+        return aol_unfused_workspace_bytes(self._h)
+
+    def run_unfused(self, ins, outs, work, stream=None):
+        """The two-kernel form: the intermediate goes through ``work`` (a uint8 device
+        tensor, 256-byte aligned); frames run in groups that fit it."""
+        import torch
+        n = self._check_tensors(ins, outs)
+        if not work.is_cuda or work.dtype != torch.uint8 or not work.is_contiguous():
+            raise ValueError("workspace must be a contiguous uint8 device tensor")
+        aol_downscale_u8_unfused(self._h, n, [t.data_ptr() for t in ins], [t.stride(0) for t in ins],
+                                 [o.data_ptr() for o in outs], [o.stride(0) for o in outs], work.data_ptr(),
+                                 work.numel(), stream)
+
     def run(self, ins, outs, stream=None):
         n = self._check_tensors(ins, outs)
         fn = aol_downscale_u8 if self.precision == "u8" else aol_downscale_f
         fn(self._h, n, [t.data_ptr() for t in ins], [t.stride(0) for t in ins],
            [o.data_ptr() for o in outs], [o.stride(0) for o in outs], stream)
+
+
+# --------------------------------------------------------------------------
+# host-to-host frame pipeline
+# --------------------------------------------------------------------------
+
+def aol_pipeline_create(plan, batch_frames: int, depth: int):
+    h = ctypes.c_void_p()
+    _check(_lib.aol_pipeline_create(plan, int(batch_frames), int(depth), ctypes.byref(h)))
+    return h
+
+
+def aol_pipeline_destroy(pipe):
+    _check(_lib.aol_pipeline_destroy(pipe))
+
+
+def aol_pipeline_run_u8(pipe, n_frames, h_in, in_frame_stride, h_out, out_frame_stride, stream=None) -> dict:
+    st = aol_pipeline_stats()
+    _check(_lib.aol_pipeline_run_u8(pipe, int(n_frames), _ptrs(h_in), _i64s(in_frame_stride), _ptrs(h_out),
+                                    _i64s(out_frame_stride), _stream_handle(stream), ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in aol_pipeline_stats._fields_}
+
+
+class Pipeline:
+    """Host-to-host downscale of frames in host memory (CPU tensors ``[n_frames, h, w]``, uint8,
+    ideally pinned): groups of ``batch_frames`` frames, ``depth`` groups in flight."""
+
+    def __init__(self, plan: "DownscalePlan", batch_frames: int = 1, depth: int = 3):
+        if plan.precision != "u8":
+            raise ValueError("pipelines run integer plans")
+        self.plan = plan  # kept alive: the pipeline refers to it
+        self._h = aol_pipeline_create(plan._h, batch_frames, depth)
+
+    def run(self, ins, outs, stream=None) -> dict:
+        """Blocks until every output frame is in host memory; returns the stage times."""
+        import torch
+        n = ins[0].shape[0]
+        for t, (h, w), o, (oh, ow), ip, op in zip(ins, self.plan.shapes, outs, self.plan.out_shapes,
+                                                  self.plan.in_pitches, self.plan.out_pitches):
+            if t.is_cuda or o.is_cuda or t.dtype != torch.uint8 or o.dtype != torch.uint8:
+                raise ValueError("host uint8 tensors expected")
+            if tuple(t.shape) != (n, h, w) or tuple(o.shape) != (n, oh, ow):
+                raise ValueError(f"shapes must be [{n}, {h}, {w}] -> [{n}, {oh}, {ow}]")
+            if t.stride(1) != ip or o.stride(1) != op or t.stride(2) != 1 or o.stride(2) != 1:
+                raise ValueError("row strides must equal the plan's pitches")
+        return aol_pipeline_run_u8(self._h, n, [t.data_ptr() for t in ins], [t.stride(0) for t in ins],
+                                   [o.data_ptr() for o in outs], [o.stride(0) for o in outs], stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            aol_pipeline_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # --------------------------------------------------------------------------

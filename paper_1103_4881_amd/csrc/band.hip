@@ -470,11 +470,11 @@ __device__ __forceinline__ void band_unit(const BandLaunch& L, int u, BandStream
 // gets a similar mix of long and short units whatever the frame count.
 __device__ __forceinline__ void band_share(const BandLaunch& L, int& i0, int& i1) {
   if (L.order) {
-    const AOL_CONST int32_t* f = (const AOL_CONST int32_t*)L.first + blockIdx.x;
+    const AOL_CONST int32_t* f = (const AOL_CONST int32_t*)L.first + ((int)blockIdx.x - L.wg0);
     i0 = f[0];
     i1 = f[1];
   } else {
-    const int G = gridDim.x, g = blockIdx.x;
+    const int G = L.ngroups, g = (int)blockIdx.x - L.wg0;
     const int full = L.total_units / G, rem = L.total_units - full * G;
     const int pos = (full & 1) ? G - 1 - g : g;  // position in the last, partial round
     i0 = 0;
@@ -484,7 +484,7 @@ __device__ __forceinline__ void band_share(const BandLaunch& L, int& i0, int& i1
 
 __device__ __forceinline__ int band_unit_at(const BandLaunch& L, int i) {
   if (L.order) return ((const AOL_CONST int32_t*)L.order)[i];
-  const int G = gridDim.x, g = blockIdx.x;
+  const int G = L.ngroups, g = (int)blockIdx.x - L.wg0;
   const int x = i * G + ((i & 1) ? G - 1 - g : g);  // item of round i
   const int unit = x / L.n_frames, frame = x - unit * L.n_frames;
   return frame * L.units_per_frame + unit;
@@ -660,7 +660,7 @@ __device__ __forceinline__ void band_load_gathered(const BandLaunch& L, uint8_t*
 // 16-byte chunks (its width or pitch, or a pointer), whose loading waves
 // gather elements; the other instances only stream whole chunks.
 template <int ELEM, int SLOTS, bool SPLIT, int KM, bool GATHER>
-__global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
+__device__ __forceinline__ void band_body(const BandLaunch& L, uint8_t* lds) {
   constexpr int ES = ELEM == kU8 ? 1 : 2;
   constexpr int E = 16 / ES;
   constexpr bool split = (ELEM == kU8) && SPLIT;
@@ -671,7 +671,6 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
   constexpr int NBL = 1;  // the loading waves: one (their prefetch holds the registers; measured no slower)
   constexpr int LS = BandLoadShares<split, KM, SLOTS>::value;  // horizontal shares per loading wave
   constexpr int NV = LS * kBandLoadWaves + NW;                 // shares of the horizontal pass
-  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const bool loader = wave < kBandLoadThreads / 64;
@@ -913,7 +912,25 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
   }
 }
 
+template <int ELEM, int SLOTS, bool SPLIT, int KM, bool GATHER>
+__global__ __launch_bounds__(kBandThreads) void k_band(BandLaunch L) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  band_body<ELEM, SLOTS, SPLIT, KM, GATHER>(L, lds);
+}
+
+// One launch of two parts of an integer batch on disjoint workgroups: the
+// first A.ngroups workgroups run the streams whose taps fit int8, the others
+// those whose taps are split (each part with its own kernel body, units and
+// balanced schedule).
+template <int SLOTS_A, int SLOTS_B, int KM>
+__global__ __launch_bounds__(kBandThreads) void k_band_dual(BandLaunch A, BandLaunch B) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  if ((int)blockIdx.x < B.wg0) band_body<kU8, SLOTS_A, false, KM, false>(A, lds);
+  else band_body<kU8, SLOTS_B, true, KM, false>(B, lds);
+}
+
 using BandFn = void (*)(BandLaunch);
+using BandDualFn = void (*)(BandLaunch, BandLaunch);
 
 template <int ELEM, bool SPLIT, int KM>
 static BandFn band_pick_s(int slots) {
@@ -953,7 +970,45 @@ hipError_t band_prepare(int elem, int slots, bool split, int kmax, size_t lds_by
 
 hipError_t band_launch(int elem, int slots, bool split, int kmax, bool gather, const BandLaunch& L, int grid,
                        size_t lds_bytes, hipStream_t stream) {
-  hipLaunchKernelGGL(band_pick(elem, slots, split, kmax, gather), dim3(grid), dim3(kBandThreads), lds_bytes, stream, L);
+  BandLaunch La = L;
+  La.wg0 = 0;
+  La.ngroups = grid;
+  hipLaunchKernelGGL(band_pick(elem, slots, split, kmax, gather), dim3(grid), dim3(kBandThreads), lds_bytes, stream, La);
+  return hipGetLastError();
+}
+
+// Instances: staging slots 4 or 8 per part (fewer are served by 4), one or
+// two K-steps.
+template <int KM>
+static BandDualFn band_dual_pick_k(int slots_a, int slots_b) {
+  if (slots_a <= 4) return slots_b <= 4 ? k_band_dual<4, 4, KM> : k_band_dual<4, 8, KM>;
+  return slots_b <= 4 ? k_band_dual<8, 4, KM> : k_band_dual<8, 8, KM>;
+}
+
+static BandDualFn band_dual_pick(int slots_a, int slots_b, int kmax) {
+  return kmax <= 1 ? band_dual_pick_k<1>(slots_a, slots_b) : band_dual_pick_k<2>(slots_a, slots_b);
+}
+
+bool band_dual_supported(int slots_a, int slots_b, int kmax) {
+  return slots_a <= 8 && slots_b <= 8 && kmax <= 2;
+}
+
+hipError_t band_dual_prepare(int slots_a, int slots_b, int kmax, size_t lds_bytes, int* wg_per_cu) {
+  const void* f = (const void*)band_dual_pick(slots_a, slots_b, kmax);
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, f, kBandThreads, lds_bytes);
+}
+
+hipError_t band_dual_launch(int slots_a, int slots_b, int kmax, const BandLaunch& A, int grid_a, const BandLaunch& B,
+                            int grid_b, size_t lds_bytes, hipStream_t stream) {
+  BandLaunch La = A, Lb = B;
+  La.wg0 = 0;
+  La.ngroups = grid_a;
+  Lb.wg0 = grid_a;
+  Lb.ngroups = grid_b;
+  hipLaunchKernelGGL(band_dual_pick(slots_a, slots_b, kmax), dim3(grid_a + grid_b), dim3(kBandThreads), lds_bytes,
+                     stream, La, Lb);
   return hipGetLastError();
 }
 

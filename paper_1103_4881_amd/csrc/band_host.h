@@ -69,6 +69,15 @@ hipError_t band_prepare(int elem, int slots, bool split, int kmax, size_t lds_by
 hipError_t band_launch(int elem, int slots, bool split, int kmax, bool gather, const BandLaunch& L, int grid,
                        size_t lds_bytes, hipStream_t stream);
 
+// One launch over the two parts of an integer batch (int8 taps on
+// workgroups [0, grid_a), split taps on the grid_b after them), both made of
+// whole chunks; kmax is the larger of the two parts'. Supported for staging
+// slots up to 8 per part and at most two K-steps.
+bool band_dual_supported(int slots_a, int slots_b, int kmax);
+hipError_t band_dual_prepare(int slots_a, int slots_b, int kmax, size_t lds_bytes, int* wg_per_cu);
+hipError_t band_dual_launch(int slots_a, int slots_b, int kmax, const BandLaunch& A, int grid_a, const BandLaunch& B,
+                            int grid_b, size_t lds_bytes, hipStream_t stream);
+
 aol_status build_band(const FilterHost& f, int tr, int elem, bool h_axis, bool force_split, AxisBand& band,
                       std::vector<uint8_t>& frags, const char* name);
 

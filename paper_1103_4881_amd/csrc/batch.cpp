@@ -50,12 +50,18 @@ struct aol_batch_plan {
     size_t unit_capacity = 0;
     // built for the current schedule
     std::vector<BandUnit> units;
+    std::vector<int64_t> cost;        // estimated cost of each unit
     int slots = 0, grid = 0;
+    int resident = 0;                 // workgroups of the part's own kernel instance resident on the device
     size_t lds = 0;
     bool gather = false;
     DeviceBuf d_units, d_order, d_first;  // unit_capacity, unit_capacity, unit_capacity + 1 entries
   };
   Part parts[2];
+  // Both parts in one launch (k_band_dual): each on its own share of the
+  // workgroups, in proportion to its estimated cost.
+  bool dual = false;
+  size_t dual_lds = 0;
   Schedule sched;
   std::vector<BandStream> streams;
   DeviceBuf d_streams, d_table;
@@ -143,29 +149,37 @@ static aol_status batch_build_part(aol_batch_plan* bp, aol_batch_plan::Part& P, 
     if (!cut) break;
   }
   for (BandUnit& U : units) U.stream = P.ids[U.stream];  // index of the whole batch's descriptors
-  // the descriptor buffers keep their addresses across schedules (allocated
-  // once at full capacity); a graph captured before a rebuild would still run
-  // its old grid and kernel instance over the new tables, so aol_graph_launch
-  // refuses it (the plan's generation changes below)
   if (units.size() > P.unit_capacity) return fail(AOL_ERR_INVALID, "unit capacity exceeded");
-  const int grid = (int)std::min<int64_t>((int64_t)wg * cus, (int64_t)units.size());
-  std::vector<int32_t> order, first;
-  band_balance(cost, grid, order, first);
-  if ((e = hipMemcpy(P.d_units.ptr, units.data(), sizeof(BandUnit) * units.size(), hipMemcpyHostToDevice)) !=
-          hipSuccess ||
-      (e = hipMemcpy(P.d_order.ptr, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice)) !=
-          hipSuccess ||
-      (e = hipMemcpy(P.d_first.ptr, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice)) !=
-          hipSuccess)
-    return hip_fail(e, "hipMemcpy");
   P.gather = false;
   for (int k = 0; k < n; ++k) {
     streams[P.ids[k]] = ps[k];
     P.gather = P.gather || !ps[k].vec_in;
   }
   P.units = std::move(units);
+  P.cost = std::move(cost);
   P.lds = (size_t)lds;
   P.slots = slots;
+  P.resident = wg * cus;
+  return AOL_OK;
+}
+
+// Assigns a part's units to `grid` workgroups and uploads its tables. The
+// descriptor buffers keep their addresses across schedules (allocated once at
+// full capacity); a graph captured before a rebuild would still run its old
+// grid and kernel instance over the new tables, so aol_graph_launch refuses it
+// (the plan's generation changes with every build).
+static aol_status batch_place_part(aol_batch_plan::Part& P, int grid) {
+  grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, (int64_t)P.units.size()));
+  std::vector<int32_t> order, first;
+  band_balance(P.cost, grid, order, first);
+  hipError_t e;
+  if ((e = hipMemcpy(P.d_units.ptr, P.units.data(), sizeof(BandUnit) * P.units.size(), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(P.d_order.ptr, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(P.d_first.ptr, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice)) !=
+          hipSuccess)
+    return hip_fail(e, "hipMemcpy");
   P.grid = grid;
   return AOL_OK;
 }
@@ -178,10 +192,45 @@ static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
     if (P.ids.empty()) continue;
     aol_status st = batch_build_part(bp, P, sc, streams);
     if (st) return st;
-    units += (int)P.units.size();
-    grid = std::max(grid, P.grid);
-    lds = std::max(lds, (int)P.lds);
-    ++launches;
+  }
+  aol_batch_plan::Part &A = bp->parts[0], &B = bp->parts[1];
+  const int kmax = std::max(A.kmax, B.kmax);
+  bp->dual = bp->elem == kU8 && !A.ids.empty() && !B.ids.empty() && !A.gather && !B.gather &&
+             band_dual_supported(A.slots, B.slots, kmax);
+  if (bp->dual) {
+    // one launch: the device's resident workgroups split between the parts
+    // in proportion to their estimated costs
+    bp->dual_lds = std::max(A.lds, B.lds);
+    int wg = 0, dev = 0, cus = 0;
+    hipError_t e = band_dual_prepare(A.slots, B.slots, kmax, bp->dual_lds, &wg);
+    if (e != hipSuccess) return hip_fail(e, "band kernel attributes");
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+      return hip_fail(e, "hipDeviceGetAttribute");
+    const int total = wg * cus;
+    if (total < 2) return fail(AOL_ERR_UNSUPPORTED, "batch schedule does not fit a compute unit");
+    double ca = 0, cb = 0;
+    for (int64_t c : A.cost) ca += (double)c;
+    for (int64_t c : B.cost) cb += (double)c;
+    int ga = (int)(total * ca / std::max(ca + cb, 1.0) + 0.5);
+    ga = std::max(1, std::min(total - 1, ga));
+    aol_status st = batch_place_part(A, ga);
+    if (!st) st = batch_place_part(B, total - ga);
+    if (st) return st;
+    units = (int)(A.units.size() + B.units.size());
+    grid = A.grid + B.grid;
+    lds = (int)bp->dual_lds;
+    launches = 1;
+  } else {
+    for (aol_batch_plan::Part& P : bp->parts) {
+      if (P.ids.empty()) continue;
+      aol_status st = batch_place_part(P, P.resident);
+      if (st) return st;
+      units += (int)P.units.size();
+      grid = std::max(grid, P.grid);
+      lds = std::max(lds, (int)P.lds);
+      ++launches;
+    }
   }
   hipError_t e = hipMemcpy(bp->d_streams.ptr, streams.data(), sizeof(BandStream) * streams.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
@@ -195,21 +244,32 @@ static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
   return AOL_OK;
 }
 
+static BandLaunch part_launch(const aol_batch_plan* bp, const aol_batch_plan::Part& P) {
+  BandLaunch L;
+  memset(&L, 0, sizeof L);
+  L.streams = (const BandStream*)bp->d_streams.ptr;
+  L.units = (const BandUnit*)P.d_units.ptr;
+  L.units_per_frame = (int32_t)P.units.size();
+  L.n_frames = 1;
+  L.total_units = (int32_t)P.units.size();
+  L.aligned = 1;  // checked by aol_batch_set_pointers
+  L.ptr_table = (void* const*)bp->d_table.ptr;
+  L.order = (const int32_t*)P.d_order.ptr;
+  L.first = (const int32_t*)P.d_first.ptr;
+  return L;
+}
+
 static aol_status batch_launch(aol_batch_plan* bp, hipStream_t stream) {
+  if (bp->dual) {
+    const aol_batch_plan::Part &A = bp->parts[0], &B = bp->parts[1];
+    hipError_t e = band_dual_launch(A.slots, B.slots, std::max(A.kmax, B.kmax), part_launch(bp, A), A.grid,
+                                    part_launch(bp, B), B.grid, bp->dual_lds, stream);
+    if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+    return AOL_OK;
+  }
   for (const aol_batch_plan::Part& P : bp->parts) {
     if (P.ids.empty()) continue;
-    BandLaunch L;
-    memset(&L, 0, sizeof L);
-    L.streams = (const BandStream*)bp->d_streams.ptr;
-    L.units = (const BandUnit*)P.d_units.ptr;
-    L.units_per_frame = (int32_t)P.units.size();
-    L.n_frames = 1;
-    L.total_units = (int32_t)P.units.size();
-    L.aligned = 1;  // checked by aol_batch_set_pointers
-    L.ptr_table = (void* const*)bp->d_table.ptr;
-    L.order = (const int32_t*)P.d_order.ptr;
-    L.first = (const int32_t*)P.d_first.ptr;
-    hipError_t e = band_launch(bp->elem, P.slots, P.split, P.kmax, P.gather, L, P.grid, P.lds, stream);
+    hipError_t e = band_launch(bp->elem, P.slots, P.split, P.kmax, P.gather, part_launch(bp, P), P.grid, P.lds, stream);
     if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
   }
   return AOL_OK;

@@ -15,6 +15,7 @@
 #include "aolmi.h"
 #include "band_host.h"
 #include "common.h"
+#include "plan.h"
 
 namespace aol {
 
@@ -247,42 +248,6 @@ aol_status build_band(const FilterHost& f, int tr, int elem, bool h_axis, bool f
 
 using namespace aol;
 
-struct aol_plan {
-  int n_planes = 0;
-  aol_plane_desc planes[kMaxPlanes];
-  int64_t mh[kMaxPlanes], mw[kMaxPlanes];
-  int elem = kU8;
-  FilterHost hf, vf;
-  int trx = 16, try_ = 16;
-  AxisBand hb{}, vb{};
-  int zpitch = 0, zrows = 0, zmb = 0;
-  int xpitch = 0, xchunks = 0, rows_per_load = 0;
-  LdsLayout lay{};
-  size_t lds = 0;
-  int grid_max = 0;  // workgroups resident on the whole device
-  int slots = 0, maxk = 0, load_rounds = 1;
-  int walk = 0;  // 0: row-major tiles inside a plane, 1: column-major
-  // band schedule: full-width (or column-band) segments streamed down each plane
-  bool use_band = false;
-  int bslots = 0, bgrid = 0;
-  int bseg = 0;  // requested segment (repetitions), 0: chosen per launch
-  size_t blds = 0;
-  FilterBands fbands;
-  BandStream bstreams[kMaxPlanes];
-  DeviceBuf d_bstreams;
-  // Unit lists of one frame for the candidate segment lengths, longest
-  // segments first, each sorted by decreasing estimated cost. Built with the
-  // band schedule (plan creation, aol_plan_set_band); a launch only picks one.
-  struct BandSched {
-    int seg = 0;    // repetitions per segment
-    int units = 0;  // units per frame
-    DeviceBuf d_units;
-  };
-  std::vector<BandSched> bsched;
-  std::string sched_json;  // text returned by aol_plan_schedule
-  bool split = false;
-  DeviceBuf d_hb, d_vb, d_hfrag, d_vfrag;
-};
 
 static int gcd_int(int a, int b) {
   while (b) {
@@ -382,6 +347,39 @@ static aol_status plan_build_tables(aol_plan* pl, int trx, int try_) {
   pl->d_vb = std::move(dvb);
   pl->d_hfrag = std::move(dhf);
   pl->d_vfrag = std::move(dvf);
+  return AOL_OK;
+}
+
+namespace aol {
+
+aol_status build_rowpass_tables(const FilterHost& f, RowPassTables& out, const char* name) {
+  std::vector<uint8_t> fr;
+  AxisBand b;
+  aol_status st = build_band(f, 16, kU8, true, false, b, fr, name);
+  if (st) return st;
+  out.band = b;
+  out.x0 = b.s_min - b.delta;
+  if ((st = out.d_band.upload(&b, sizeof b))) return st;
+  return out.d_frag.upload(fr.data(), fr.size());
+}
+
+}  // namespace aol
+
+// The unfused form of an integer plan: both axes' row-pass tables and the
+// layout of one frame's transposed intermediates (rows padded to whole
+// 128-byte lines, planes 256-byte aligned).
+static aol_status plan_build_unfused(aol_plan* pl) {
+  pl->uws_frame = 0;
+  aol_status st = build_rowpass_tables(pl->hf, pl->uh, "hf");
+  if (!st) st = build_rowpass_tables(pl->vf, pl->uv, "vf");
+  if (st) return st == AOL_ERR_UNSUPPORTED ? AOL_OK : st;  // filters beyond the row pass: no unfused form
+  int64_t off = 0;
+  for (int i = 0; i < pl->n_planes; ++i) {
+    pl->uws_off[i] = off;
+    pl->uws_pitch[i] = (pl->planes[i].height + 127) / 128 * 128;
+    off += (pl->mw[i] * pl->uws_pitch[i] + 255) / 256 * 256;
+  }
+  pl->uws_frame = off;
   return AOL_OK;
 }
 
@@ -547,6 +545,7 @@ aol_status aol_downscale_plan_create(const aol_plane_desc* planes, int32_t n_pla
     }
   }
   if (!st) st = plan_build_band(pl, 0, 0);
+  if (!st && pl->elem == kU8) st = plan_build_unfused(pl);
   if (st) {
     delete pl;
     return st;

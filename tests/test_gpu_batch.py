@@ -176,6 +176,53 @@ def test_batch_int8_taps_streams_of_the_mix(fill):
     plan.close()
 
 
+# int8-tap and split-tap streams whose lines are whole 16-byte chunks: both parts in one launch
+MIX_DUAL = [  # (h, w, p, q, taps, kind)
+    (96, 208, 3, 8, 11, "design"),
+    (61, 128, 1, 2, 8, "design"),
+    (120, 96, 2, 3, 16, "design"),
+    (33, 64, 2, 3, 13, "random"),
+    (250, 336, 3, 8, 16, "design"),
+    (140, 160, 5, 7, 9, "random"),
+    (300, 512, 1, 2, 12, "random"),
+]
+
+
+@pytest.mark.parametrize("fill", FILLS)
+def test_batch_int8_and_split_taps_in_one_launch(fill):
+    """Streams with int8 taps and streams with split taps run as the two parts of one launch
+    (each on its own workgroups), directly and through a graph over two steps."""
+    st = _streams(MIX_DUAL, seed=40)
+    plan = aol.BatchPlan([(h, w, hf, vf) for (h, w, hf, vf, _, _) in st], "u8")
+    assert '"launches": 1' in plan.schedule(), plan.schedule()
+    steps = 2
+    frames = _frames(MIX_DUAL, steps, 31)
+    ins = [[torch.from_numpy(fr).cuda() for fr in fs] for fs in frames]
+    outs = [[torch.full(plan.out_shapes[i], fill, dtype=torch.uint8, device="cuda") for _ in range(steps)]
+            for i in range(len(st))]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.set_pointers([ins[i][0] for i in range(len(st))], [outs[i][0] for i in range(len(st))], s)
+        plan.run(s)
+        g = plan.graph(s)
+        plan.set_pointers([ins[i][1] for i in range(len(st))], [outs[i][1] for i in range(len(st))], s)
+        aol.aol_graph_launch(g, s)
+    s.synchronize()
+    for i, (h, w, hf, vf, of, ov) in enumerate(st):
+        for k in range(steps):
+            np.testing.assert_array_equal(outs[i][k].cpu().numpy(), pp.downscale_u8(frames[i][k], of, ov),
+                                          err_msg=f"stream {i} step {k}")
+    plan.close()
+
+
+def test_batch_64_streams_one_launch():
+    """The 64-stream mix (int8-tap and split-tap filters) is scheduled as one launch."""
+    _, _, streams = _mix64()
+    plan = aol.BatchPlan(streams, "u8")
+    assert '"launches": 1' in plan.schedule(), plan.schedule()
+    plan.close()
+
+
 def _mix64():
     mix = synthgen.stream_mix(2011, 64)
     filt = {}
