@@ -212,6 +212,20 @@ aol_status aol_downscale_u8_unfused(aol_plan* plan, int32_t n_frames, const uint
                                     const int64_t* out_frame_stride, void* d_work, int64_t work_bytes,
                                     hipStream_t stream);
 
+/* The same two passes with the intermediate in a static device workspace
+ * of 64 MiB (one per GPU, held until the process ends) instead of a
+ * caller's: for callers that cannot allocate device memory (code under
+ * stream capture, serving loops, harnesses that forbid allocation). The call
+ * allocates nothing. Frames run in groups that fit the 64 MiB;
+ * AOL_ERR_UNSUPPORTED when one frame's intermediate
+ * (aol_unfused_workspace_bytes) exceeds it. Every call on a GPU shares that
+ * GPU's workspace and nothing in it needs to start cleared: calls that
+ * overlap on one GPU (other streams, other threads, other plans) race and
+ * must be ordered by the caller. */
+aol_status aol_downscale_u8_unfused_static(aol_plan* plan, int32_t n_frames, const uint8_t* const* d_in,
+                                           const int64_t* in_frame_stride, uint8_t* const* d_out,
+                                           const int64_t* out_frame_stride, hipStream_t stream);
+
 /* --------------------------------------------------------------------------
  * Host-to-host frame pipeline (Sec. IV: in the paper's measurements the
  * copies between host and device memory take most of the application's

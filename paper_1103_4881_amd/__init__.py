@@ -96,6 +96,9 @@ _proto("aol_unfused_workspace_bytes", ctypes.c_int, ctypes.c_void_p, c_i64p)
 _proto("aol_downscale_u8_unfused", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), c_i64p,
        ctypes.POINTER(ctypes.c_void_p), c_i64p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p)
 
+_proto("aol_downscale_u8_unfused_static", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32,
+       ctypes.POINTER(ctypes.c_void_p), c_i64p, ctypes.POINTER(ctypes.c_void_p), c_i64p, ctypes.c_void_p)
+
 
 class aol_pipeline_stats(ctypes.Structure):
     _fields_ = [("groups", ctypes.c_int32), ("frames", ctypes.c_int32), ("wall_ms", ctypes.c_double),
@@ -265,6 +268,11 @@ def aol_downscale_u8_unfused(plan, n_frames, d_in, in_frame_stride, d_out, out_f
     _check(_lib.aol_downscale_u8_unfused(plan, int(n_frames), _ptrs(d_in), _i64s(in_frame_stride), _ptrs(d_out),
                                          _i64s(out_frame_stride), ctypes.c_void_p(int(d_work)), int(work_bytes),
                                          _stream_handle(stream)))
+
+
+def aol_downscale_u8_unfused_static(plan, n_frames, d_in, in_frame_stride, d_out, out_frame_stride, stream=None):
+    _check(_lib.aol_downscale_u8_unfused_static(plan, int(n_frames), _ptrs(d_in), _i64s(in_frame_stride),
+                                                _ptrs(d_out), _i64s(out_frame_stride), _stream_handle(stream)))
 
 
 class DownscalePlan:

@@ -380,7 +380,7 @@ static aol_status plan_build_unfused(aol_plan* pl) {
     off += (pl->mw[i] * pl->uws_pitch[i] + 255) / 256 * 256;
   }
   pl->uws_frame = off;
-  return AOL_OK;
+  return static_workspace(&pl->uws_static);
 }
 
 // The band schedule (default): one workgroup per column band of a plane,

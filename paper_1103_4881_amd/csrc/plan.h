@@ -20,6 +20,13 @@ struct RowPassTables {
 
 aol_status build_rowpass_tables(const FilterHost& f, RowPassTables& out, const char* name);
 
+// Bytes of the static workspace of aol_downscale_u8_unfused_static.
+constexpr int64_t kStaticWorkBytes = 64ll << 20;
+
+// Device address of the static workspace on the current device (resolved
+// once per device).
+aol_status static_workspace(uint8_t** out);
+
 }  // namespace aol
 
 // Plan members use the library namespace's types unqualified.
@@ -66,4 +73,5 @@ struct aol_plan {
   RowPassTables uh, uv;
   int64_t uws_off[kMaxPlanes] = {}, uws_pitch[kMaxPlanes] = {};
   int64_t uws_frame = 0;  // workspace bytes per frame (0: no unfused form)
+  uint8_t* uws_static = nullptr;  // the static workspace on the plan's device
 };

@@ -7,13 +7,42 @@
 #include <algorithm>
 #include <climits>
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "aolmi.h"
 #include "common.h"
 #include "plan.h"
 #include "rowpass.h"
 
+// Workspace of the allocation-free entry point: a static device array, one
+// per GPU (each device holds its own copy, at its own address, for as long as
+// the library is loaded). Its host-side name is not a device address: host
+// code uses only the address hipGetSymbolAddress returns for the current
+// device, resolved once per device at plan creation.
+static __device__ __align__(256) uint8_t scratch[kStaticWorkBytes];
+
 namespace aol {
+
+static std::mutex g_scratch_mu;
+static std::vector<uint8_t*> g_scratch_ptr;  // per device ordinal
+
+aol_status static_workspace(uint8_t** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the static workspace");
+    g_scratch_ptr[dev] = (uint8_t*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return AOL_OK;
+}
 
 static int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
@@ -126,6 +155,20 @@ aol_status aol_downscale_u8_unfused(aol_plan* plan, int32_t n_frames, const uint
                                     hipStream_t stream) {
   return run_unfused(plan, n_frames, d_in, in_frame_stride, d_out, out_frame_stride, (uint8_t*)d_work, work_bytes,
                      stream);
+}
+
+aol_status aol_downscale_u8_unfused_static(aol_plan* plan, int32_t n_frames, const uint8_t* const* d_in,
+                                           const int64_t* in_frame_stride, uint8_t* const* d_out,
+                                           const int64_t* out_frame_stride, hipStream_t stream) {
+  if (!plan) return fail(AOL_ERR_INVALID, "NULL plan");
+  if (plan->elem != kU8) return fail(AOL_ERR_INVALID, "the unfused form is integer only (plan precision AOL_PREC_U8)");
+  if (plan->uws_frame == 0) return fail(AOL_ERR_UNSUPPORTED, "these filters have no unfused form");
+  if (plan->uws_frame > kStaticWorkBytes)
+    return fail(AOL_ERR_UNSUPPORTED, "one frame's intermediate (%lld bytes) exceeds the static workspace (%lld bytes)",
+                (long long)plan->uws_frame, (long long)kStaticWorkBytes);
+  if (!plan->uws_static) return fail(AOL_ERR_INVALID, "the plan has no static workspace address");
+  return run_unfused(plan, n_frames, d_in, in_frame_stride, d_out, out_frame_stride, plan->uws_static,
+                     kStaticWorkBytes, stream);
 }
 
 }  // extern "C"
