@@ -198,6 +198,81 @@ def bench_unfused(u8, Yh, Uh, Vh, steps, warmup):
                             "bytes": round(bytes_unf / u8["bytes"], 3)}}
 
 
+LIN_FRAMES = 30
+VALU_MAC_PEAK = 256 * 64 * 2 * 2.4e9  # v_dot2_i32_i16: 2 MACs per lane, a wave64 instruction per CU and cycle
+
+
+def _frames_spec(spec, frames):
+    """A tiler spec with a leading frame dimension in the array and the repetition space."""
+    import synthgen
+    paving = [[1] + [0] * len(spec.paving[0])] + [[0] + list(row) for row in spec.paving]
+    fitting = [[0] * len(spec.fitting[0])] + [list(row) for row in spec.fitting]
+    return synthgen.TilerSpec((frames,) + tuple(spec.array_shape), (0,) + tuple(spec.origin), paving, fitting,
+                              spec.pat_shape)
+
+
+def bench_linear(steps=20, warmup=10, n=LIN_FRAMES):
+    """The linear integer repetition (wider elementary tasks): interleaved RGB 1920x1080 frames to
+    planar colour components (3 -> 3 per pixel), the composition back to RGB, and a non-separable
+    2-D polyphase downscale of luma frames (3/8 on both axes, 11 x 11 kernels per output phase:
+    a 17 x 17 window -> 3 x 3 outputs per repetition); frames as a repetition dimension."""
+    import torch
+    import paper_1103_4881_amd as aol
+    import synthgen
+    from oracle import linear as ln
+    from oracle.arrayol import Tiler
+    h, w = H, W
+    ot = lambda sp: Tiler(sp.array_shape, sp.origin, sp.paving, sp.fitting, sp.pat_shape)
+    at = lambda sp, rep: aol.make_tiler(sp.array_shape, rep, sp.pat_shape, sp.origin, sp.paving, sp.fitting)
+    res = {}
+    stream = torch.cuda.current_stream()
+    rgb = np.stack([synthgen.uniform_frame(SEED + 7 + f, h, 3 * w) for f in range(n)])
+    rep0, tin0, tout0 = synthgen.rgb_to_planar_tilers(h, w)
+    rep20, tin20, tout20 = synthgen.planar_to_rgb_tilers(h, w)
+    rep_p, tin_p, tout_p, _, span = synthgen.polyphase2d_tilers(h, w, P, Q, TAPS)
+    Wp = synthgen.polyphase2d_weights(SEED, P, Q, TAPS)
+    x_rgb = torch.from_numpy(rgb).cuda()
+    planar = torch.empty((n, 3, h, w), dtype=torch.uint8, device="cuda")
+    back = torch.empty((n, h, 3 * w), dtype=torch.uint8, device="cuda")
+    luma = x_rgb.view(n, h, 3 * w)[:, :, :w].contiguous()
+    down = torch.empty((n, P * -(-h // Q), P * -(-w // Q)), dtype=torch.uint8, device="cuda")
+    cases = [("rgb_to_planar_ycc", x_rgb, planar, rep0, tin0, tout0, synthgen.RGB_TO_YCC_W, synthgen.RGB_TO_YCC_BIAS),
+             ("planar_ycc_to_rgb", planar, back, rep20, tin20, tout20, synthgen.YCC_TO_RGB_W,
+              synthgen.YCC_TO_RGB_BIAS),
+             ("polyphase2d_3_8_11x11", luma, down, rep_p, tin_p, tout_p, Wp, None)]
+    for name, x, y, rep1, ti1, to1, Wt, bias in cases:
+        rep, ti, to = (n,) + tuple(rep1), _frames_spec(ti1, n), _frames_spec(to1, n)
+        plan = aol.LinearPlan(at(ti, rep), at(to, rep), Wt, bias)
+        ms_step, ms_kernel, ms_med = time_launches(lambda: plan.run(x, y), steps, warmup, stream)
+        plan.close()
+        torch.cuda.synchronize()
+        n_in, n_out = int(np.prod(ti1.pat_shape)), int(np.prod(to1.pat_shape))
+        nrep = int(np.prod(rep))
+        alg_bytes = x.numel() + y.numel()  # every input element read once, every output written once
+        mism = 0
+        xh = x.cpu().numpy()
+        yh = y.cpu().numpy()
+        for f in (0, n - 1):
+            ref, _ = ln.linear_u8(xh[f], ot(ti1), Wt, bias, ot(to1), rep1)
+            mism += int((yh[f] != ref).sum())
+        gbs = alg_bytes / (ms_kernel / 1e3) / 1e9
+        macs = nrep * n_in * n_out
+        e = {"ms_per_step": round(ms_step, 4), "kernel_ms_median": round(ms_med, 4), "frames": n,
+             "repetitions": nrep, "pattern_in": n_in, "pattern_out": n_out, "alg_bytes": alg_bytes,
+             "hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4)},
+             "mismatches_first_last_frame": mism}
+        tmac = macs / (ms_kernel / 1e3) / 1e12
+        e["alu"] = {"achieved": round(tmac, 2), "peak": round(VALU_MAC_PEAK / 1e12, 1), "unit": "TMAC/s",
+                    "frac": round(tmac * 1e12 / VALU_MAC_PEAK, 4), "macs_per_launch": macs}
+        e["bound"] = "hbm" if e["hbm"]["frac"] >= e["alu"]["frac"] else "alu"
+        res[name] = e
+        log(f"linear {name}: {ms_step:.3f} ms/step, {gbs:.0f} GB/s, {tmac:.1f} TMAC/s, mismatches {mism}")
+    del x_rgb, planar, back, luma, down
+    torch.cuda.empty_cache()
+    return res
+
+
 CIF_FRAMES = 2000
 
 
@@ -560,7 +635,7 @@ def main():
     ap.add_argument("--cpu-single-frames", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-float", action="store_true")
-    ap.add_argument("--only", choices=["u8", "unfused", "bf16", "fp16", "batch", "generic", "config1", "cif"], default=None,
+    ap.add_argument("--only", choices=["u8", "unfused", "bf16", "fp16", "batch", "generic", "linear", "config1", "cif"], default=None,
                     help="run one workload only (for profiling)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-generic", action="store_true")
@@ -654,7 +729,9 @@ def main():
     if not args.no_generic and args.only in (None, "generic"):
         extra["generic"] = bench_generic()
         log(f"generic: {extra['generic']['ms_per_step']:.3f} ms/step")
-    if args.only in ("batch", "generic"):
+    if not args.no_generic and args.only in (None, "linear"):
+        extra["linear_u8"] = bench_linear()
+    if args.only in ("batch", "generic", "linear"):
         print(json.dumps({"metric": METRIC, **extra}), flush=True)
         return
 

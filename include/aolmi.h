@@ -15,8 +15,9 @@
  *  - Device buffers are plain device pointers owned by the caller. Plans own
  *    the device tables they allocate at creation (filter fragments, tile
  *    lists, pointer tables) and free them on destroy.
- *  - Run calls (aol_downscale_u8, aol_downscale_f, aol_batch_run,
- *    aol_graph_launch, aol_wsum_run) only enqueue work on the given stream:
+ *  - Run calls (aol_downscale_u8, aol_downscale_f, aol_downscale_u8_unfused,
+ *    aol_downscale_u8_unfused_static, aol_batch_run, aol_graph_launch,
+ *    aol_wsum_run, aol_linear_run) only enqueue work on the given stream:
  *    they never allocate and never synchronise. They check pointers and
  *    alignment and report launch errors; faults inside a kernel surface at
  *    the caller's next synchronisation.
@@ -385,6 +386,40 @@ aol_status aol_wsum_plan_destroy(aol_wsum_plan* plan);
  * aol_wsum_plan_create and aol_wsum_run. */
 aol_status aol_weighted_sum_f32(const aol_tiler* in, const aol_tiler* out, const float* weights, const float* d_in,
                                 float* d_out, hipStream_t stream);
+
+/* --------------------------------------------------------------------------
+ * General Array-OL repetition with a linear integer elementary task (uint8).
+ *
+ * Sec. III: the application takes 24-bit RGB frames apart into colour
+ * components, filters them and composes the output frame; Sec. III-A: every
+ * step is a repetitive task with an input and an output tiler. For every
+ * point r of the repetition space
+ *
+ *   x[i] = in[(o + P.r + F.i) mod S]                   (input pattern, row-major)
+ *   y[j] = clamp(floor((sum_i W[j][i] * x[i] + bias[j] + 128) / 256), 0, 255)
+ *   out[(o' + P'.r + F'.j) mod S'] = y[j]              (output pattern, row-major)
+ *
+ * computed exactly (int32 sums). With three-byte patterns this converts
+ * interleaved RGB to planar colour components and back (the composition of
+ * the frame); with a T x T input pattern and a p x p output pattern it is a
+ * non-separable 2-D filter with several outputs per repetition.
+ * weights: host, int16 [n_out][n_in] (n_in = prod(in->pat_shape) <= 1024,
+ * n_out = prod(out->pat_shape) <= 16); bias: host int32 [n_out] or NULL; both
+ * copied into the plan. Both tilers share the repetition space (at most
+ * 2^31 - 1 points); arrays are dense row-major uint8 below 2^31 elements.
+ * Plan creation checks that the output tiler writes every element of its
+ * array exactly once (walking the repetition space on the host;
+ * AOL_ERR_INVALID otherwise) and that no sum can leave int32
+ * (AOL_ERR_UNSUPPORTED).
+ * ------------------------------------------------------------------------ */
+typedef struct aol_linear_plan aol_linear_plan;
+
+aol_status aol_linear_plan_create(const aol_tiler* in, const aol_tiler* out, const int16_t* weights,
+                                  const int32_t* bias, aol_linear_plan** plan);
+/* d_in: prod(in->array_shape) bytes; d_out: prod(out->array_shape) bytes; must
+ * not alias. Enqueue only. */
+aol_status aol_linear_run(aol_linear_plan* plan, const uint8_t* d_in, uint8_t* d_out, hipStream_t stream);
+aol_status aol_linear_plan_destroy(aol_linear_plan* plan);
 
 #ifdef __cplusplus
 }

@@ -147,6 +147,11 @@ _proto("aol_wsum_plan_destroy", ctypes.c_int, ctypes.c_void_p)
 _proto("aol_weighted_sum_f32", ctypes.c_int, ctypes.POINTER(aol_tiler), ctypes.POINTER(aol_tiler),
        ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
+_proto("aol_linear_plan_create", ctypes.c_int, ctypes.POINTER(aol_tiler), ctypes.POINTER(aol_tiler), c_i16p,
+       c_i32p, ctypes.POINTER(ctypes.c_void_p))
+_proto("aol_linear_run", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_proto("aol_linear_plan_destroy", ctypes.c_int, ctypes.c_void_p)
+
 
 def _check(status: int):
     if status != AOL_OK:
@@ -498,6 +503,58 @@ class WeightedSumPlan:
     def close(self):
         if getattr(self, "_h", None):
             aol_wsum_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------------------
+# linear integer repetition (uint8)
+# --------------------------------------------------------------------------
+
+def aol_linear_plan_create(tin: aol_tiler, tout: aol_tiler, weights, bias=None):
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.int16).ravel())
+    b = None if bias is None else np.ascontiguousarray(np.asarray(bias, dtype=np.int32).ravel())
+    h = ctypes.c_void_p()
+    _check(_lib.aol_linear_plan_create(ctypes.byref(tin), ctypes.byref(tout), w.ctypes.data_as(c_i16p),
+                                       None if b is None else b.ctypes.data_as(c_i32p), ctypes.byref(h)))
+    return h
+
+
+def aol_linear_run(plan, d_in, d_out, stream=None):
+    _check(_lib.aol_linear_run(plan, ctypes.c_void_p(int(d_in)), ctypes.c_void_p(int(d_out)), _stream_handle(stream)))
+
+
+def aol_linear_plan_destroy(plan):
+    _check(_lib.aol_linear_plan_destroy(plan))
+
+
+class LinearPlan:
+    """``out[(o' + P'.r + F'.j) mod S'] = clamp(floor((sum_i W[j][i] in[(o + P.r + F.i) mod S]
+    + bias[j] + 128) / 256), 0, 255)`` on uint8 device tensors."""
+
+    def __init__(self, tin: aol_tiler, tout: aol_tiler, weights, bias=None):
+        self.in_shape = tuple(tin.array_shape[d] for d in range(tin.array_rank))
+        self.out_shape = tuple(tout.array_shape[d] for d in range(tout.array_rank))
+        self._h = aol_linear_plan_create(tin, tout, weights, bias)
+
+    def run(self, x, y, stream=None):
+        import torch
+        if x.dtype != torch.uint8 or y.dtype != torch.uint8 or not (x.is_cuda and y.is_cuda):
+            raise ValueError("uint8 device tensors expected")
+        if tuple(x.shape) != self.in_shape or tuple(y.shape) != self.out_shape:
+            raise ValueError(f"shapes must be {self.in_shape} -> {self.out_shape}")
+        if not (x.is_contiguous() and y.is_contiguous()):
+            raise ValueError("contiguous tensors expected")
+        aol_linear_run(self._h, x.data_ptr(), y.data_ptr(), stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            aol_linear_plan_destroy(self._h)
             self._h = None
 
     def __del__(self):

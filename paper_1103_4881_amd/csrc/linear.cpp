@@ -1,0 +1,232 @@
+// Host side of the Array-OL repetition with a linear integer elementary task:
+// tiler validation, the output tiler's exact-coverage check, pattern tables.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "aolmi.h"
+#include "common.h"
+#include "linear.h"
+
+using namespace aol;
+
+struct aol_linear_plan {
+  LinearArgs args{};
+  int nout = 1;  // kernel instance: output pattern elements rounded up to 1, 2, 3, 4, 6, 8, 9, 12 or 16
+  DeviceBuf d_tab;
+};
+
+namespace {
+
+int64_t pmod64(int64_t a, int64_t m) {
+  const int64_t r = a % m;
+  return r < 0 ? r + m : r;
+}
+
+int64_t count(const int64_t* shape, int rank) {
+  int64_t n = 1;
+  for (int k = 0; k < rank; ++k) n *= shape[k];
+  return n;
+}
+
+aol_status check_tiler(const aol_tiler* t, const char* name, int max_pat) {
+  if (!t) return fail(AOL_ERR_INVALID, "%s: NULL tiler", name);
+  if (t->array_rank < 1 || t->rep_rank < 1 || t->pat_rank < 0)
+    return fail(AOL_ERR_INVALID, "%s: ranks must be >= 1 (pattern >= 0)", name);
+  if (t->array_rank > AOL_MAX_RANK || t->rep_rank > AOL_MAX_RANK || t->pat_rank > AOL_MAX_RANK)
+    return fail(AOL_ERR_UNSUPPORTED, "%s: ranks above %d", name, AOL_MAX_RANK);
+  int64_t n = 1;
+  for (int d = 0; d < t->array_rank; ++d) {
+    if (t->array_shape[d] < 1) return fail(AOL_ERR_INVALID, "%s: array_shape[%d] < 1", name, d);
+    n *= t->array_shape[d];
+    if (n >= (1LL << 31)) return fail(AOL_ERR_UNSUPPORTED, "%s: arrays of 2^31 elements or more", name);
+  }
+  int64_t nr = 1;
+  for (int k = 0; k < t->rep_rank; ++k) {
+    if (t->rep_shape[k] < 1) return fail(AOL_ERR_INVALID, "%s: rep_shape[%d] < 1", name, k);
+    nr *= t->rep_shape[k];
+    if (nr >= (1LL << 31)) return fail(AOL_ERR_UNSUPPORTED, "%s: repetition spaces of 2^31 points or more", name);
+  }
+  int64_t np = 1;
+  for (int b = 0; b < t->pat_rank; ++b) {
+    if (t->pat_shape[b] < 1) return fail(AOL_ERR_INVALID, "%s: pat_shape[%d] < 1", name, b);
+    np *= t->pat_shape[b];
+    if (np > max_pat) return fail(AOL_ERR_UNSUPPORTED, "%s: patterns of more than %d elements", name, max_pat);
+  }
+  return AOL_OK;
+}
+
+// Pattern element i of tiler t: its fitting offset along each array dim.
+void fitting_offsets(const aol_tiler* t, int i, int64_t* f) {
+  int64_t idx[AOL_MAX_RANK] = {0, 0, 0, 0};
+  int rem = i;
+  for (int b = t->pat_rank - 1; b >= 0; --b) {
+    idx[b] = rem % t->pat_shape[b];
+    rem /= (int)t->pat_shape[b];
+  }
+  for (int d = 0; d < t->array_rank; ++d) {
+    f[d] = 0;
+    for (int b = 0; b < t->pat_rank; ++b) f[d] += t->fitting[d][b] * idx[b];
+  }
+}
+
+// One side (input or output) of the launch arguments: shape, strides,
+// origin and paving reduced mod the shape, the extents of the pattern's
+// offsets (patterns inside the array use flat offsets: a pattern longer than
+// an axis always takes the wrapping path), the per-thread step along the last
+// repetition dim; fills the flat and per-dim offset tables.
+void side(const aol_tiler* t, int n_pat, int n_pad, int32_t* S, int32_t* st, int32_t* o, int32_t (*P)[kLinRank],
+          int32_t* lo, int32_t* hi, int32_t* inc, std::vector<int32_t>& off, std::vector<int32_t>& fd) {
+  const int ra = t->array_rank, rr = t->rep_rank;
+  int64_t s = 1;
+  for (int d = ra - 1; d >= 0; --d) {
+    S[d] = (int32_t)t->array_shape[d];
+    st[d] = (int32_t)s;
+    s *= t->array_shape[d];
+  }
+  for (int d = 0; d < ra; ++d) {
+    o[d] = (int32_t)pmod64(t->origin[d], S[d]);
+    for (int k = 0; k < rr; ++k) P[d][k] = (int32_t)pmod64(t->paving[d][k], S[d]);
+    inc[d] = (int32_t)pmod64((int64_t)kLinThreads * t->paving[d][rr - 1], S[d]);
+    lo[d] = 0;
+    hi[d] = 0;
+  }
+  off.assign((size_t)n_pad, 0);
+  fd.assign((size_t)ra * n_pad, 0);
+  for (int i = 0; i < n_pad; ++i) {
+    int64_t f[AOL_MAX_RANK];
+    fitting_offsets(t, i < n_pat ? i : 0, f);  // padding repeats element 0 (its weights are zero)
+    int64_t flat = 0;
+    for (int d = 0; d < ra; ++d) {
+      if (f[d] <= -S[d] || f[d] >= S[d]) {  // longer than the axis: no point counts as inside
+        lo[d] = -S[d];
+        hi[d] = S[d];
+      } else {
+        lo[d] = (int32_t)std::min<int64_t>(lo[d], f[d]);
+        hi[d] = (int32_t)std::max<int64_t>(hi[d], f[d]);
+      }
+      fd[(size_t)d * n_pad + i] = (int32_t)pmod64(f[d], S[d]);
+      flat += std::max<int64_t>(std::min<int64_t>(f[d], S[d]), -S[d]) * st[d];
+    }
+    off[(size_t)i] = (int32_t)flat;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+aol_status aol_linear_plan_create(const aol_tiler* in, const aol_tiler* out, const int16_t* weights,
+                                  const int32_t* bias, aol_linear_plan** plan) {
+  if (!plan) return fail(AOL_ERR_INVALID, "NULL plan output");
+  *plan = nullptr;
+  aol_status st = check_tiler(in, "in", kLinMaxIn);
+  if (!st) st = check_tiler(out, "out", kLinMaxOut);
+  if (st) return st;
+  if (!weights) return fail(AOL_ERR_INVALID, "NULL weights");
+  if (out->rep_rank != in->rep_rank) return fail(AOL_ERR_INVALID, "input and output repetition ranks differ");
+  for (int k = 0; k < in->rep_rank; ++k)
+    if (out->rep_shape[k] != in->rep_shape[k]) return fail(AOL_ERR_INVALID, "repetition spaces differ");
+  const int n_in = (int)count(in->pat_shape, in->pat_rank);
+  const int n_out = (int)count(out->pat_shape, out->pat_rank);
+  const int64_t nrep = count(in->rep_shape, in->rep_rank);
+  // int32 accumulation must be exact: |sum_i W x + bias + 128| < 2^31 for any x in 0..255
+  for (int j = 0; j < n_out; ++j) {
+    int64_t m = 128 + (bias ? std::abs((int64_t)bias[j]) : 0);
+    for (int i = 0; i < n_in; ++i) m += 255 * std::abs((int64_t)weights[(size_t)j * n_in + i]);
+    if (m >= (1LL << 31)) return fail(AOL_ERR_UNSUPPORTED, "output %d: weights too large for exact int32 sums", j);
+  }
+  // exact coverage: the output tiler writes every element of its array once
+  const int64_t out_elems = count(out->array_shape, out->array_rank);
+  if (out_elems != nrep * n_out)
+    return fail(AOL_ERR_INVALID, "output array has %lld elements for %lld repetitions x %d pattern elements",
+                (long long)out_elems, (long long)nrep, n_out);
+  {
+    std::vector<uint8_t> seen((size_t)out_elems, 0);
+    std::vector<int64_t> ofs((size_t)n_out * out->array_rank);
+    for (int j = 0; j < n_out; ++j) fitting_offsets(out, j, &ofs[(size_t)j * out->array_rank]);
+    int64_t r[AOL_MAX_RANK] = {0, 0, 0, 0};
+    for (int64_t n = 0; n < nrep; ++n) {
+      for (int j = 0; j < n_out; ++j) {
+        int64_t flat = 0;
+        for (int d = 0; d < out->array_rank; ++d) {
+          int64_t v = out->origin[d] + ofs[(size_t)j * out->array_rank + d];
+          for (int k = 0; k < out->rep_rank; ++k) v += out->paving[d][k] * r[k];
+          flat = flat * out->array_shape[d] + pmod64(v, out->array_shape[d]);
+        }
+        if (seen[(size_t)flat]) return fail(AOL_ERR_INVALID, "output tiler writes an element twice (not a bijection)");
+        seen[(size_t)flat] = 1;
+      }
+      for (int k = out->rep_rank - 1; k >= 0; --k) {
+        if (++r[k] < out->rep_shape[k]) break;
+        r[k] = 0;
+      }
+    }
+  }
+
+  aol_linear_plan* p = new (std::nothrow) aol_linear_plan();
+  if (!p) return fail(AOL_ERR_NOMEM, "plan allocation");
+  LinearArgs& a = p->args;
+  for (int v : {1, 2, 3, 4, 6, 8, 9, 12, 16})
+    if (n_out <= v) {
+      p->nout = v;
+      break;
+    }
+  const int NOUT = p->nout;
+  const int n_pairs = (n_in + 1) / 2, n_pad = 2 * n_pairs;
+  a.nrep = nrep;
+  a.rr = in->rep_rank;
+  for (int k = 0; k < a.rr; ++k) a.R[k] = (int32_t)in->rep_shape[k];
+  a.ra = in->array_rank;
+  a.ro = out->array_rank;
+  a.n_pairs = n_pairs;
+  a.n_out = n_out;
+  std::vector<int32_t> ioff, ifd, ooff, ofd;
+  side(in, n_in, n_pad, a.S, a.st, a.o, a.P, a.lo, a.hi, a.inc, ioff, ifd);
+  side(out, n_out, NOUT, a.So, a.sto, a.oo, a.Po, a.olo, a.ohi, a.oinc, ooff, ofd);
+  // the table: ioff, ifd, packed weight pairs, bias + 128, ooff, ofd
+  std::vector<int32_t> tab(ioff);
+  a.t_ifd = (int32_t)tab.size();
+  tab.insert(tab.end(), ifd.begin(), ifd.end());
+  a.t_w = (int32_t)tab.size();
+  for (int k = 0; k < n_pairs; ++k)
+    for (int j = 0; j < NOUT; ++j) {
+      auto w = [&](int i) -> uint32_t {
+        return (j < n_out && i < n_in) ? (uint16_t)weights[(size_t)j * n_in + i] : 0u;
+      };
+      tab.push_back((int32_t)(w(2 * k) | (w(2 * k + 1) << 16)));
+    }
+  a.t_bias = (int32_t)tab.size();
+  for (int j = 0; j < NOUT; ++j) tab.push_back((j < n_out && bias ? bias[j] : 0) + 128);
+  a.t_ooff = (int32_t)tab.size();
+  tab.insert(tab.end(), ooff.begin(), ooff.end());
+  a.t_ofd = (int32_t)tab.size();
+  tab.insert(tab.end(), ofd.begin(), ofd.end());
+  if ((st = p->d_tab.upload(tab.data(), tab.size() * sizeof(int32_t)))) {
+    delete p;
+    return st;
+  }
+  a.tab = (const int32_t*)p->d_tab.ptr;
+  *plan = p;
+  return ok();
+}
+
+aol_status aol_linear_run(aol_linear_plan* plan, const uint8_t* d_in, uint8_t* d_out, hipStream_t stream) {
+  if (!plan) return fail(AOL_ERR_INVALID, "NULL plan");
+  if (!d_in || !d_out) return fail(AOL_ERR_INVALID, "NULL buffer");
+  LinearArgs a = plan->args;
+  a.in = d_in;
+  a.out = d_out;
+  hipError_t e = linear_launch(plan->nout, a, stream);
+  if (e != hipSuccess) return hip_fail(e, "linear task launch");
+  return ok();
+}
+
+aol_status aol_linear_plan_destroy(aol_linear_plan* plan) {
+  delete plan;
+  return ok();
+}
+
+}  // extern "C"
