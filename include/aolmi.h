@@ -346,8 +346,10 @@ const char* aol_batch_schedule(aol_batch_plan* plan);
  *
  *   out[(o' + P'.r) mod S'] = sum_i w[i] * in[(o + P.r + F.i) mod S]
  *
- * in float32 (weights and data float32, accumulation in pattern order with
- * fused multiply-adds). Arrays are dense row-major float32 buffers owned by
+ * in float32 (weights and data float32, fused multiply-adds; a plan may sum
+ * the pattern grouped by the reads neighbouring points share, so the
+ * rounding can differ from a sum in pattern order, always within float32's
+ * bound for npat terms). Arrays are dense row-major float32 buffers owned by
  * the caller. paving is array_rank x rep_rank, fitting array_rank x pat_rank,
  * both as [array dim][other dim]; unused entries are ignored. The output
  * tiler must have a single-element pattern (pat_rank 0) and the same

@@ -21,7 +21,12 @@ struct aol_wsum_plan {
   WsumArgs args{};
   int64_t blocks = 0;
   int64_t in_elems = 0, out_elems = 0;
+  DeviceBuf d_ctab;  // staged form: per-block terms of the box origins
 };
+
+// Largest corner table (entries) a plan builds; beyond it the box origins
+// are computed on the device.
+static constexpr int64_t kWsumMaxCornerEntries = 1 << 22;
 
 static int64_t pmod64(int64_t a, int64_t m) {
   int64_t r = a % m;
@@ -57,9 +62,10 @@ static aol_status check_tiler(const aol_tiler* t, const char* name, bool output)
   return AOL_OK;
 }
 
-extern "C" {
-
-aol_status aol_wsum_plan_create(const aol_tiler* in, const aol_tiler* out, const float* weights, aol_wsum_plan** plan) {
+// device_tables: the plan may keep a device table (plans); the one-shot
+// entry point allocates nothing on the device.
+static aol_status wsum_create(const aol_tiler* in, const aol_tiler* out, const float* weights, bool device_tables,
+                              aol_wsum_plan** plan) {
   if (!plan) return fail(AOL_ERR_INVALID, "NULL plan output");
   *plan = nullptr;
   aol_status st = check_tiler(in, "in", false);
@@ -215,6 +221,8 @@ aol_status aol_wsum_plan_create(const aol_tiler* in, const aol_tiler* out, const
   }
   a.nb_lane = (int32_t)((R[k_lane] + 63) / 64);
   a.nb_loop = (int32_t)((R[k_loop] + 63) / 64);
+  auto magic = [](int64_t d) { return (uint32_t)(((uint64_t)1 << 32) / (uint64_t)d + 1); };
+  for (int k = 0; k < a.rr; ++k) a.mg_R[k] = magic(R[k]);
   a.n_other = 0;
   int64_t blocks = (int64_t)a.nb_lane * a.nb_loop;
   for (int k = 0; k < a.rr; ++k) {
@@ -302,11 +310,94 @@ aol_status aol_wsum_plan_create(const aol_tiler* in, const aol_tiler* out, const
         delete p;
         return hip_fail(e, "weighted-sum kernel attributes");
       }
+      // Per repetition dim k and block index b_k along it (corner rc_k =
+      // b_k * extent: 64 along the lanes, the block's points along the loop,
+      // 1 elsewhere): the term Ps[d][k] * rc_k mod S[d] of the box origin.
+      int64_t nb[kWsumMaxRank], total = 0;
+      for (int k = 0; k < a.rr; ++k) {
+        nb[k] = k == k_lane ? a.nb_lane : k == k_loop ? a.nb_loop : R[k];
+        total += nb[k] * a.ra;
+      }
+      if (device_tables && total <= kWsumMaxCornerEntries) {
+        std::vector<int32_t> tab;
+        tab.reserve((size_t)total);
+        for (int k = 0; k < a.rr; ++k) {
+          const int64_t ext = k == k_lane ? 64 : k == k_loop ? 4 * kWsumBoxPoints : 1;
+          a.ctab_off[k] = (int32_t)tab.size();
+          for (int64_t b = 0; b < nb[k]; ++b)
+            for (int d = 0; d < a.ra; ++d) tab.push_back((int32_t)pmod64((int64_t)a.Ps[d][k] * (b * ext), a.S[d]));
+        }
+        for (int d = 0; d < a.ra; ++d) a.c0[d] = (int32_t)pmod64((int64_t)a.o[d] + a.dlo[d], a.S[d]);
+        // classes of pattern elements whose box offsets differ by multiples of jstep
+        const int64_t js = a.jstep;
+        std::vector<int64_t> keys;
+        std::vector<std::vector<std::pair<int64_t, float>>> members;
+        if (js != 0) {
+          const int64_t aj = js < 0 ? -js : js;
+          for (int i = 0; i < npat; ++i) {
+            const int64_t key = pmod64(a.offl[i], aj);
+            const int64_t m = (a.offl[i] - key) / js;
+            size_t c = 0;
+            while (c < keys.size() && keys[c] != key) ++c;
+            if (c == keys.size()) {
+              keys.push_back(key);
+              members.emplace_back();
+            }
+            members[c].push_back({m, weights[i]});
+          }
+        }
+        int width = 0;
+        for (const auto& mem : members) {
+          int64_t lo_m = mem[0].first, hi_m = mem[0].first;
+          for (const auto& x : mem) {
+            lo_m = std::min(lo_m, x.first);
+            hi_m = std::max(hi_m, x.first);
+          }
+          width = (int)std::max<int64_t>(width, hi_m - lo_m + 1);
+        }
+        int em = 0;
+        for (int w : kWsumClassWidths)
+          if (!em && width <= w) em = w;
+        // worth it when a class shares reads (fewer reads than one per element and point)
+        if (js != 0 && em && (int64_t)keys.size() * (em + kWsumBoxPoints - 1) < (int64_t)npat * kWsumBoxPoints) {
+          a.ctab_cls = (int32_t)tab.size();
+          for (size_t c = 0; c < keys.size(); ++c) {
+            int64_t lo_m = members[c][0].first;
+            for (const auto& x : members[c]) lo_m = std::min(lo_m, x.first);
+            std::vector<float> wv((size_t)em, 0.f);
+            for (const auto& x : members[c]) wv[(size_t)(x.first - lo_m)] += x.second;
+            tab.push_back((int32_t)(keys[c] + lo_m * js));  // box offset of the class's first multiple
+            tab.push_back(0);
+            for (float f : wv) {
+              int32_t bits;
+              memcpy(&bits, &f, 4);
+              tab.push_back(bits);
+            }
+          }
+          a.ncls = (int32_t)keys.size();
+          a.em = em;
+        }
+        aol_status ust = p->d_ctab.upload(tab.data(), tab.size() * sizeof(int32_t));
+        if (ust) {
+          delete p;
+          return ust;
+        }
+        a.ctab = (const int32_t*)p->d_ctab.ptr;
+        if (a.em) a.cls = a.ctab + a.ctab_cls;
+      }
     }
   }
+  a.mg_lane = magic(a.nb_lane);
+  a.mg_loop = magic(a.nb_loop);
   p->blocks = blocks;
   *plan = p;
   return ok();
+}
+
+extern "C" {
+
+aol_status aol_wsum_plan_create(const aol_tiler* in, const aol_tiler* out, const float* weights, aol_wsum_plan** plan) {
+  return wsum_create(in, out, weights, true, plan);
 }
 
 aol_status aol_wsum_run(aol_wsum_plan* plan, const float* d_in, float* d_out, hipStream_t stream) {
@@ -329,9 +420,9 @@ aol_status aol_wsum_plan_destroy(aol_wsum_plan* plan) {
 aol_status aol_weighted_sum_f32(const aol_tiler* in, const aol_tiler* out, const float* weights, const float* d_in,
                                 float* d_out, hipStream_t stream) {
   aol_wsum_plan* plan = nullptr;
-  aol_status st = aol_wsum_plan_create(in, out, weights, &plan);
+  aol_status st = wsum_create(in, out, weights, false, &plan);
   if (st) return st;
-  st = aol_wsum_run(plan, d_in, d_out, stream);  // the plan holds host data only: freed at once
+  st = aol_wsum_run(plan, d_in, d_out, stream);  // without device tables the plan is host data only: freed at once
   delete plan;
   return st;
 }

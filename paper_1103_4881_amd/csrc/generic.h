@@ -29,6 +29,7 @@ struct WsumArgs {
   int64_t ostr_rep[kWsumMaxRank];        // identity output: stride of each repetition dim
   int32_t k_lane, k_loop;                // repetition dims along lanes / along each thread's loop
   int32_t nb_lane, nb_loop;              // 64-wide blocks along k_lane / k_loop
+  uint32_t mg_lane, mg_loop, mg_R[kWsumMaxRank];  // floor(2^32 / divisor) + 1 of nb_lane, nb_loop, R
   int32_t other[kWsumMaxRank];
   int32_t n_other;
   int32_t transpose;                     // stage results in LDS and store along k_loop
@@ -44,7 +45,26 @@ struct WsumArgs {
   int32_t box_elems;
   int32_t lstep, jstep;                  // box offset per lane / per loop point
   int32_t offl[kMaxPat];                 // box offset of each pattern element (dlo folded in)
+  // Box origins without 64-bit arithmetic on the device: lo[d] = (c0[d] +
+  // sum_k ctab[ctab_off[k] + b_k * ra + d]) mod S[d], b_k the block's index
+  // along repetition dim k (every term already reduced mod S[d]); NULL: the
+  // origin is computed directly.
+  const int32_t* ctab;
+  int32_t ctab_off[kWsumMaxRank];
+  int32_t c0[kWsumMaxRank];
+  // Staged form, values shared along the loop dimension: pattern elements
+  // whose box offsets differ by a multiple of jstep read, at neighbouring
+  // points, the same box elements. Class c (ncls of them) lists its offset
+  // key and first multiple mmin, then em weights (float bits) for the
+  // multiples mmin .. mmin + em - 1 (zero where no element sits): point j
+  // adds sum_e w[e] * box[base + key + (mmin + e + j) * jstep]. NULL: one
+  // read per pattern element and point.
+  const int32_t* cls;
+  int32_t ncls, em;
+  int32_t ctab_cls;  // host: offset of the class table inside the device table
 };
+
+constexpr int kWsumClassWidths[] = {3, 5, 8};  // kernel instances by the widest class
 
 constexpr int kWsumBoxMaxBytes = 48 * 1024;  // box in LDS per workgroup
 constexpr int kWsumBoxPoints = 8;            // staged form: points per thread along the loop dimension

@@ -18,9 +18,15 @@
 //
 // Staged form (BOX): when the input elements a block of points reads lie in a
 // box small enough for LDS, the workgroup first loads that box (rows along
-// the input's contiguous axis, the modulo wrap applied while loading), then
-// every pattern element of every point is an LDS read at a constant offset
-// from the point's base; each input element comes from HBM once per block.
+// the input's contiguous axis, the modulo wrap applied while loading; the
+// rows' wrapped offsets computed by the lanes in parallel, the box origin
+// from a host table of per-block terms), then every pattern element of
+// every point is an LDS read at a constant offset from the point's base;
+// each input element comes from HBM once per block. Pattern elements whose
+// offsets differ by a multiple of the loop dimension's step read, at
+// neighbouring points of a thread, the same box elements: such a class is
+// read once per thread (PT + width - 1 reads) and weighted as a sliding
+// window.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -32,6 +38,7 @@ namespace aol {
 // pointers taken from a by-value argument structure are generic to the
 // compiler, and generic accesses become flat instructions.
 typedef const __attribute__((address_space(1))) float* gin_t;
+#define AOL_WCONST __attribute__((address_space(4)))
 typedef __attribute__((address_space(1))) float* gout_t;
 
 // Weighted sum of one pattern: the gathers are issued 8 at a time, so that
@@ -70,10 +77,48 @@ __device__ __forceinline__ void wsum_box_points(const WsumArgs& a, const float* 
   }
 }
 
+// floor(n / d) for n, d < 2^31 from m = floor(2^32 / d) + 1: the product's
+// high word is the quotient or one more, corrected by one comparison.
+__device__ __forceinline__ uint32_t wsum_div(uint32_t n, uint32_t d, uint32_t m) {
+  if (d == 1) return n;  // m would be 2^32 + 1
+  uint32_t q = __umulhi(n, m);
+  return q * d > n ? q - 1 : q;
+}
+
+// Staged form with reads shared along the loop dimension: per class, the
+// box values of its multiples at the thread's PT points (PT + width - 1
+// reads, the rest zero), then each multiple's weight times a sliding window
+// of them.
+template <int PT, int EM>
+__device__ __forceinline__ void wsum_box_classes(const WsumArgs& a, const float* pb0, float (&acc)[PT]) {
+  const AOL_WCONST int32_t* ct = (const AOL_WCONST int32_t*)a.cls;
+#pragma unroll
+  for (int j = 0; j < PT; ++j) acc[j] = 0.f;
+  for (int c = 0; c < a.ncls; ++c) {
+    const AOL_WCONST int32_t* e = ct + c * (2 + EM);
+    const float* p = pb0 + e[0];  // the class's first multiple: key + mmin * jstep
+    float w[EM];
+    int nv = PT;  // values the class reads: PT + (its widest nonzero multiple)
+#pragma unroll
+    for (int m = 0; m < EM; ++m) {
+      w[m] = __int_as_float(e[2 + m]);
+      if (e[2 + m] != 0) nv = PT + m;
+    }
+    float v[PT + EM - 1];
+#pragma unroll
+    for (int t = 0; t < PT + EM - 1; ++t) v[t] = t < nv ? p[t * a.jstep] : 0.f;  // uniform bound
+#pragma unroll
+    for (int m = 0; m < EM; ++m)
+#pragma unroll
+      for (int j = 0; j < PT; ++j) acc[j] = __builtin_fmaf(w[m], v[j + m], acc[j]);
+  }
+}
+
 // PT: points per thread along the loop dimension (a block is 64 x 4*PT
 // points): 16 for the direct form, 8 for the staged form (a smaller box, so
 // more workgroups per compute unit overlap their loads with others' sums).
-template <bool BOX>
+// EM: the widest class of shared reads (0: one read per pattern element).
+template <bool BOX, int EM>
 __global__ __launch_bounds__(256) void k_wsum(WsumArgs a) {
   constexpr int PT = BOX ? 8 : 16;
   constexpr int BJ = 4 * PT;  // block extent along the loop dimension
@@ -86,17 +131,20 @@ __global__ __launch_bounds__(256) void k_wsum(WsumArgs a) {
   // in 32 bits (fewer than 2^31 blocks); arrays indexed by unrolled
   // constants only, so they stay in scalar registers
   uint32_t blk = blockIdx.x;
-  const int bl = (int)(blk % (uint32_t)a.nb_lane);
-  blk /= (uint32_t)a.nb_lane;
-  const int bp = (int)(blk % (uint32_t)a.nb_loop);
-  blk /= (uint32_t)a.nb_loop;
+  uint32_t q = wsum_div(blk, (uint32_t)a.nb_lane, a.mg_lane);
+  const int bl = (int)(blk - q * (uint32_t)a.nb_lane);
+  blk = q;
+  q = wsum_div(blk, (uint32_t)a.nb_loop, a.mg_loop);
+  const int bp = (int)(blk - q * (uint32_t)a.nb_loop);
+  blk = q;
   int rc[kWsumMaxRank];  // the block's corner point
 #pragma unroll
   for (int k = kWsumMaxRank - 1; k >= 0; --k) {
     rc[k] = 0;
     if (k < a.rr && k != a.k_lane && k != a.k_loop) {
-      rc[k] = (int)(blk % (uint32_t)a.R[k]);
-      blk /= (uint32_t)a.R[k];
+      q = wsum_div(blk, (uint32_t)a.R[k], a.mg_R[k]);
+      rc[k] = (int)(blk - q * (uint32_t)a.R[k]);
+      blk = q;
     } else if (k == a.k_lane) {
       rc[k] = bl * 64;
     } else if (k == a.k_loop) {
@@ -137,15 +185,38 @@ __global__ __launch_bounds__(256) void k_wsum(WsumArgs a) {
   if constexpr (BOX) {
     // box origin of the block (its corner point: lane 0, loop point 0), wrapped
     int lo[kWsumMaxRank];
+    if (a.ctab) {
+      // sum of terms each reduced mod S on the host: a few subtractions wrap it
+      const AOL_WCONST int32_t* ct = (const AOL_WCONST int32_t*)a.ctab;
+      int bk[kWsumMaxRank];
 #pragma unroll
-    for (int d = 0; d < kWsumMaxRank; ++d) {
-      lo[d] = 0;
-      if (d < a.ra) {
-        int64_t v = (int64_t)a.o[d] + a.dlo[d];
+      for (int k = 0; k < kWsumMaxRank; ++k) bk[k] = k == a.k_lane ? bl : k == a.k_loop ? bp : rc[k];
 #pragma unroll
-        for (int k = 0; k < kWsumMaxRank; ++k) v += (int64_t)a.Ps[d][k] * rc[k];
-        v %= a.S[d];
-        lo[d] = (int)(v < 0 ? v + a.S[d] : v);
+      for (int d = 0; d < kWsumMaxRank; ++d) {
+        lo[d] = 0;
+        if (d < a.ra) {
+          int v = a.c0[d];
+#pragma unroll
+          for (int k = 0; k < kWsumMaxRank; ++k) {
+            if (k < a.rr) {
+              v += ct[a.ctab_off[k] + bk[k] * a.ra + d];
+              if (v >= a.S[d]) v -= a.S[d];
+            }
+          }
+          lo[d] = v;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int d = 0; d < kWsumMaxRank; ++d) {
+        lo[d] = 0;
+        if (d < a.ra) {
+          int64_t v = (int64_t)a.o[d] + a.dlo[d];
+#pragma unroll
+          for (int k = 0; k < kWsumMaxRank; ++k) v += (int64_t)a.Ps[d][k] * rc[k];
+          v %= a.S[d];
+          lo[d] = (int)(v < 0 ? v + a.S[d] : v);
+        }
       }
     }
     const int last = a.ra - 1;
@@ -168,39 +239,30 @@ __global__ __launch_bounds__(256) void k_wsum(WsumArgs a) {
     int col[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) col[k] = wrap_col(k);
-    int t[kWsumMaxRank] = {0, 0, 0, 0};  // coordinates of row `row` in the box (all dims but the last)
-    auto advance = [&](int by) {
-      for (int d = last - 1; d >= 0 && by > 0; --d) {
-        const int v = t[d] + by;
-        by = v / a.bn[d];
-        t[d] = v - by * a.bn[d];
+    // Global offset of every box row (all dims but the last, the one before
+    // the last fastest), wrapped per dim: one row per thread, into LDS
+    // after the box and the spill slots.
+    int* roff = reinterpret_cast<int*>(box + a.box_elems + 64);
+    for (int q = threadIdx.x; q < a.box_rows; q += 256) {
+      int rem = q, gg = 0;
+#pragma unroll
+      for (int d = kWsumMaxRank - 2; d >= 0; --d) {
+        if (d >= last) continue;
+        const int td = rem % a.bn[d];
+        rem /= a.bn[d];
+        int c = lo[d] + td;  // lo < S and td < extent <= 2S: two subtractions wrap it
+        if (c >= a.S[d]) c -= a.S[d];
+        if (c >= a.S[d]) c -= a.S[d];
+        gg += c * a.st[d];
       }
-    };
+      roff[q] = gg;
+    }
+    __syncthreads();
     constexpr int QR = 8;  // rows per wave and iteration
-    advance(wave * QR);
     for (int row0 = wave * QR; row0 < a.box_rows; row0 += 4 * QR) {
       int g[QR];
-      int tq[kWsumMaxRank] = {t[0], t[1], t[2], t[3]};
 #pragma unroll
-      for (int q = 0; q < QR; ++q) {
-        int gg = 0;
-#pragma unroll
-        for (int d = 0; d < kWsumMaxRank - 1; ++d) {
-          if (d >= last) break;
-          int c = lo[d] + tq[d];  // lo < S and t < extent <= 2S: two subtractions wrap it
-          if (c >= a.S[d]) c -= a.S[d];
-          if (c >= a.S[d]) c -= a.S[d];
-          gg += c * a.st[d];
-        }
-        g[q] = gg;
-        // next row (past the last row: stays in the box, loaded and not stored)
-#pragma unroll
-        for (int d = kWsumMaxRank - 2; d >= 0; --d) {
-          if (d >= last) continue;
-          if (++tq[d] < a.bn[d]) break;
-          tq[d] = 0;
-        }
-      }
+      for (int q = 0; q < QR; ++q) g[q] = roff[min(row0 + q, a.box_rows - 1)];  // past the last row: loaded, not stored
       for (int t0 = 0; t0 < nt; t0 += 4) {
         float v[QR][4];
 #pragma unroll
@@ -220,15 +282,22 @@ __global__ __launch_bounds__(256) void k_wsum(WsumArgs a) {
           for (int q = 0; q < QR; ++q) box[row0 + q < a.box_rows && tt < rowlen ? dst0 + q * rowlen : a.box_elems + lane] = v[q][k];
         }
       }
-      advance(4 * QR);
     }
     __syncthreads();
   }
   float bacc[BOX ? PT : 1];
-  if constexpr (BOX) wsum_box_points<PT>(a, box + lane * a.lstep + wave * PT * a.jstep, a.jstep, bacc);
+  if constexpr (BOX && EM > 0) wsum_box_classes<PT, EM>(a, box + lane * a.lstep + wave * PT * a.jstep, bacc);
+  else if constexpr (BOX) wsum_box_points<PT>(a, box + lane * a.lstep + wave * PT * a.jstep, a.jstep, bacc);
 
+  if constexpr (BOX) {
+    if (a.transpose) {  // the usual staged case: results go through the transposed tile
+#pragma unroll
+      for (int j = 0; j < PT; ++j) tile[lane][wave * PT + j] = bacc[j];
+    }
+  }
 #pragma unroll(BOX ? PT : 1)
   for (int j = 0; j < PT; ++j) {
+    if (BOX && a.transpose) break;  // uniform: stored above
     const int rl = r_loop0 + j;
     const bool ok = lane_ok && rl < a.R[a.k_loop];
     float acc = 0.f;
@@ -294,28 +363,44 @@ __global__ __launch_bounds__(256) void k_wsum(WsumArgs a) {
     // identity output whose contiguous dimension is the loop dimension:
     // lanes now run along it
     __syncthreads();
-    int64_t rowbase = 0;
+    // output arrays hold fewer than 2^31 elements: 32-bit offsets
+    uint32_t rowbase = 0;
     for (int k = 0; k < a.rr; ++k)
-      if (k != a.k_lane && k != a.k_loop) rowbase += r[k] * a.ostr_rep[k];
+      if (k != a.k_lane && k != a.k_loop) rowbase += (uint32_t)r[k] * (uint32_t)a.ostr_rep[k];
     const int rl = bp * BJ + lane;
-    for (int row = wave; row < 64; row += 4) {
-      const int rla = bl * 64 + row;
-      if (lane < BJ && rla < a.R[a.k_lane] && rl < a.R[a.k_loop])
-        ((gout_t)a.out)[rowbase + (int64_t)rla * a.ostr_rep[a.k_lane] + (int64_t)rl * a.ostr_rep[a.k_loop]] = tile[row][lane];
+    const uint32_t sl = (uint32_t)a.ostr_rep[a.k_lane];
+    uint32_t of = rowbase + (uint32_t)(bl * 64 + wave) * sl + (uint32_t)rl * (uint32_t)a.ostr_rep[a.k_loop];
+    const bool col_ok = lane < BJ && rl < a.R[a.k_loop];
+    for (int row = wave; row < 64; row += 4, of += 4 * sl) {
+      if (col_ok && bl * 64 + row < a.R[a.k_lane]) ((gout_t)a.out)[of] = tile[row][lane];
     }
   }
 }
 
 using WsumFn = void (*)(WsumArgs);
 
-static WsumFn wsum_pick(const WsumArgs& a) { return a.use_box ? k_wsum<true> : k_wsum<false>; }
+static WsumFn wsum_pick(const WsumArgs& a) {
+  if (!a.use_box) return k_wsum<false, 0>;
+  switch (a.cls ? a.em : 0) {
+    case 3: return k_wsum<true, 3>;
+    case 5: return k_wsum<true, 5>;
+    case 8: return k_wsum<true, 8>;
+    default: return k_wsum<true, 0>;
+  }
+}
 
 hipError_t wsum_prepare() {
-  return hipFuncSetAttribute((const void*)k_wsum<true>, hipFuncAttributeMaxDynamicSharedMemorySize, kWsumBoxMaxBytes + 256);
+  for (WsumFn f : {k_wsum<true, 0>, k_wsum<true, 3>, k_wsum<true, 5>, k_wsum<true, 8>}) {
+    hipError_t e = hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       2 * kWsumBoxMaxBytes + 256);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t wsum_launch(const WsumArgs& a, int64_t blocks, hipStream_t stream) {
-  const size_t lds = a.use_box ? (size_t)(a.box_elems + 64) * 4 : 0;  // and one spill slot per lane
+  // the box, one spill slot per lane, then the row offsets
+  const size_t lds = a.use_box ? (size_t)(a.box_elems + 64 + a.box_rows) * 4 : 0;
   hipLaunchKernelGGL(wsum_pick(a), dim3((unsigned)blocks), dim3(256), lds, stream, a);
   return hipGetLastError();
 }
