@@ -152,6 +152,7 @@ struct BandLaunch {
   const int32_t* first;
   int32_t units_per_frame, n_frames, total_units;
   int32_t wg0, ngroups;          // the launch's workgroups [wg0, wg0 + ngroups) run these units
+  int32_t grouped;               // rounds over frame-major items, the slots of one XCD consecutive
   int32_t aligned;               // every pointer 16-byte aligned (inputs) / 16-byte (outputs)
   void* const* ptr_table;        // device [in, out] pointer per stream, or NULL: use ptrs below
   const void* ptrs[2 * kMaxPlanes];

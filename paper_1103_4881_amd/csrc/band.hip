@@ -461,6 +461,17 @@ __device__ __forceinline__ void band_unit(const BandLaunch& L, int u, BandStream
   G.vec_out = S.vec_out && L.aligned;
 }
 
+// The workgroup's slot in the rounds. Workgroups are dispatched to the 8
+// XCDs in turn (workgroup g on XCD g mod 8), each XCD with its own L2; when
+// the launch groups items (column bands of one segment next to each other,
+// frame-major), the workgroups of one XCD take consecutive slots, so the
+// bands of a segment run on one XCD at the same time and the lines at their
+// shared edges are fetched from memory once.
+__device__ __forceinline__ int band_slot(const BandLaunch& L) {
+  const int G = L.ngroups, g = (int)blockIdx.x - L.wg0;
+  return (L.grouped && G % 8 == 0) ? (g % 8) * (G / 8) + g / 8 : g;
+}
+
 // Workgroup's share of the launch: positions [i0, i1) of its sequence of
 // units. With a unit order (batches) the sequence is its slice of that
 // table. Without one (downscale plans) the launch's items, the units of one
@@ -474,7 +485,7 @@ __device__ __forceinline__ void band_share(const BandLaunch& L, int& i0, int& i1
     i0 = f[0];
     i1 = f[1];
   } else {
-    const int G = L.ngroups, g = (int)blockIdx.x - L.wg0;
+    const int G = L.ngroups, g = band_slot(L);
     const int full = L.total_units / G, rem = L.total_units - full * G;
     const int pos = (full & 1) ? G - 1 - g : g;  // position in the last, partial round
     i0 = 0;
@@ -484,8 +495,9 @@ __device__ __forceinline__ void band_share(const BandLaunch& L, int& i0, int& i1
 
 __device__ __forceinline__ int band_unit_at(const BandLaunch& L, int i) {
   if (L.order) return ((const AOL_CONST int32_t*)L.order)[i];
-  const int G = L.ngroups, g = (int)blockIdx.x - L.wg0;
+  const int G = L.ngroups, g = band_slot(L);
   const int x = i * G + ((i & 1) ? G - 1 - g : g);  // item of round i
+  if (L.grouped) return x;  // frame-major items: frame * units_per_frame + unit
   const int unit = x / L.n_frames, frame = x - unit * L.n_frames;
   return frame * L.units_per_frame + unit;
 }

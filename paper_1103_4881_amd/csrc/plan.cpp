@@ -667,6 +667,9 @@ static aol_status run_fused(aol_plan* plan, int32_t n_frames, const void* const*
     L.total_units = (int32_t)items;
     L.order = nullptr;  // rounds over the workgroups, computed in the kernel
     L.first = nullptr;
+    // planes cut into column bands: their bands' shared edge lines are read once when the
+    // bands of a segment run together on one XCD
+    for (int i = 0; i < plan->n_planes; ++i) L.grouped |= plan->bstreams[i].xreps < plan->bstreams[i].rx ? 1 : 0;
     const int grid = (int)std::min<int64_t>(items, plan->bgrid);
     hipError_t e = band_launch(plan->elem, plan->bslots, plan->fbands.split, plan->fbands.kmax, gather, L, grid,
                                plan->blds, stream);

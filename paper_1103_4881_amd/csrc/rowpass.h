@@ -24,6 +24,7 @@ struct RowPassPlane {
   int32_t m;                        // outputs per row, p * ceil(n / q)
   int32_t nblocks;                  // ceil(m / 16)
   int32_t row_tiles;                // ceil(rows / kRowPassRows)
+  int32_t blk_tiles;                // ceil(nblocks / kRowPassBlocks)
   int32_t tile_base;                // first tile of the plane inside a frame
   int32_t vec_in;                   // row starts 16-byte aligned (rows of whole chunks)
   int32_t vec_out;                  // 16 or 4: output rows aligned to that many bytes, else 1
@@ -34,7 +35,7 @@ struct RowPassArgs {
   int32_t n_planes;
   int32_t tiles_per_frame;
   int32_t x0;            // element of position 0 of a period's window, relative to 16*q*period
-  int32_t pad;
+  int32_t total_tiles;   // tiles of the launch (the grid is rounded up to a multiple of 8)
   const AxisBand* band;  // one period (16 repetitions), 16-byte chunk aligned
   const void* frag;      // coefficient operands, 64 lanes x 16 bytes per K-step
 };

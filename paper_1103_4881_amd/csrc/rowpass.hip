@@ -71,17 +71,26 @@ __device__ __forceinline__ v4i rp_to_i8(v4i x) {
 // of a block (4 chunks of 16 elements each).
 template <bool SPLIT, int KM>
 __global__ __launch_bounds__(kRowPassThreads) void k_rowpass(RowPassArgs A) {
-  constexpr int NJ = (SPLIT || KM > 2) ? 2 : 4;  // blocks in flight per iteration
+  // blocks in flight per iteration (eight for one K-step measured slower: the
+  // registers cost more waves than the extra loads win)
+  constexpr int NJ = (SPLIT || KM > 2) ? 2 : 4;
   // the tile's outputs, transposed: row k = output 16*b0 + k, one byte per input row
   __shared__ __attribute__((aligned(16))) uint8_t tile_t[kRowPassBlocks * 16][kRowPassTilePitch];
-  const int tile = blockIdx.x;
+  // Workgroups go to the 8 XCDs in turn (workgroup g on XCD g mod 8), each
+  // XCD with its own L2: the workgroups of one XCD take consecutive tiles,
+  // so the neighbouring tiles of a row of tiles, which read the same lines at
+  // their edges, run one after the other on one XCD and fetch those lines
+  // once. The grid is a multiple of 8; tiles past the last are empty.
+  const int G8 = gridDim.x / 8, wg = blockIdx.x;
+  const int tile = (wg % 8) * G8 + wg / 8;
+  if (tile >= A.total_tiles) return;
   const int frame = tile / A.tiles_per_frame;
   int t = tile - frame * A.tiles_per_frame;
   int pi = 0;
   while (pi + 1 < A.n_planes && t >= A.pl[pi + 1].tile_base) ++pi;
   const RowPassPlane P = A.pl[pi];
   t -= P.tile_base;
-  const int bt = t / P.row_tiles, rt = t - bt * P.row_tiles;
+  const int rt = t / P.blk_tiles, bt = t - rt * P.blk_tiles;  // neighbouring tiles along a row of tiles
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
   const int tile_row0 = rt * kRowPassRows;

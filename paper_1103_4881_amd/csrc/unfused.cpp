@@ -88,8 +88,9 @@ static void pass_args(const aol_plan* pl, bool h, int f0, int nf, const uint8_t*
     }
     P.nblocks = ceil_div(P.m, 16);
     P.row_tiles = ceil_div(P.rows, kRowPassRows);
+    P.blk_tiles = ceil_div(P.nblocks, kRowPassBlocks);
     P.tile_base = tiles;
-    tiles += P.row_tiles * ceil_div(P.nblocks, kRowPassBlocks);
+    tiles += P.row_tiles * P.blk_tiles;
   }
   a.n_planes = pl->n_planes;
   a.tiles_per_frame = tiles;
@@ -127,8 +128,10 @@ aol_status run_unfused(aol_plan* pl, int32_t n_frames, const uint8_t* const* d_i
     for (int h = 1; h >= 0; --h) {
       RowPassArgs a;
       pass_args(pl, h != 0, f0, nf, d_in, in_fs, d_out, out_fs, work, a);
-      const int64_t grid = (int64_t)a.tiles_per_frame * nf;
+      const int64_t tiles = (int64_t)a.tiles_per_frame * nf;
+      const int64_t grid = (tiles + 7) / 8 * 8;
       if (grid > INT_MAX) return fail(AOL_ERR_UNSUPPORTED, "too many tiles in one launch");
+      a.total_tiles = (int32_t)tiles;
       const AxisBand& b = (h ? pl->uh : pl->uv).band;
       hipError_t e = rowpass_launch(b.split != 0, b.kmax, a, (int)grid, stream);
       if (e != hipSuccess) return hip_fail(e, h ? "horizontal pass launch" : "vertical pass launch");
