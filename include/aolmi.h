@@ -318,9 +318,14 @@ aol_status aol_batch_graph_create(aol_batch_plan* plan, hipStream_t stream, aol_
 aol_status aol_graph_launch(aol_graph* graph, hipStream_t stream);
 aol_status aol_graph_destroy(aol_graph* graph);
 
-/* Times the schedule candidates (segment length x column-band LDS budget)
- * on the buffers last set, keeps the fastest, and appends it to the tuning
- * cache. Synchronises the stream (not a run call); results are unchanged. */
+/* Times schedule candidates on the buffers last set: first one segment
+ * length for every stream x the column-band LDS budget (16..128 repetitions x
+ * 150 or 76 KiB), then, classes with the most input first, each stream
+ * class's own segment length (16..128; a class: the two ratios and the width
+ * class up to 640, 1280, 1920 pixels or wider) with the others held. Keeps the
+ * fastest and appends it to the tuning cache (keyed by the device
+ * architecture, the precision and the streams' sizes and filters).
+ * Synchronises the stream (not a run call); results are unchanged. */
 aol_status aol_autotune(aol_batch_plan* plan, hipStream_t stream);
 
 /* Rebuilds the plan with one schedule: segments of seg_reps repetitions (a

@@ -23,9 +23,21 @@ using namespace aol;
 namespace {
 
 struct Schedule {
-  int seg = 0;         // repetitions per segment (0: about 256 input lines)
+  int seg = 0;         // repetitions per segment (0: about 512 input lines)
   int budget = 150 * 1024;  // LDS budget per workgroup (picks the column band)
+  std::vector<int> class_seg;  // per stream class: its own segment length (0 or absent: seg)
 };
+
+// Stream classes of the tuner: ratio of each axis and width class (up to
+// 640, 1280, 1920 pixels, wider).
+struct StreamClass {
+  int hp, hq, vp, vq, wc;
+  bool operator==(const StreamClass& o) const {
+    return hp == o.hp && hq == o.hq && vp == o.vp && vq == o.vq && wc == o.wc;
+  }
+};
+
+int width_class(int64_t w) { return w <= 640 ? 0 : w <= 1280 ? 1 : w <= 1920 ? 2 : 3; }
 
 bool same_filter(const FilterHost& a, const FilterHost& b) {
   return a.p == b.p && a.q == b.q && a.taps == b.taps && a.c == b.c && a.s == b.s;
@@ -39,6 +51,8 @@ struct aol_batch_plan {
   std::vector<aol_stream_desc> desc;  // (filter pointers are not kept)
   std::vector<FilterHost> hf, vf;
   std::vector<int> filt;              // filter group of each stream
+  std::vector<int> cls;               // tuner class of each stream
+  std::vector<int64_t> cls_bytes;     // input bytes of each class (the tuner's order)
   std::vector<FilterBands> bands;     // one per filter group
   // The streams whose filters fit int8 taps and those that need the split
   // operands run as two launches (each with its own kernel instance), so
@@ -127,7 +141,9 @@ static aol_status batch_build_part(aol_batch_plan* bp, aol_batch_plan::Part& P, 
   std::vector<int> segs(n);
   for (int k = 0; k < n; ++k) {
     const int q = fbs[k]->vb.q;
-    const int want = sc.seg > 0 ? sc.seg : 16 * ((512 + 16 * q - 1) / (16 * q));
+    const int c = bp->cls[P.ids[k]];
+    const int cs = c < (int)sc.class_seg.size() ? sc.class_seg[c] : 0;
+    const int want = cs > 0 ? cs : sc.seg > 0 ? sc.seg : 16 * ((512 + 16 * q - 1) / (16 * q));
     segs[k] = std::max(16, std::min(want, band_max_seg(fbs[k]->vb)));
   }
   std::vector<BandUnit> units;
@@ -238,9 +254,11 @@ static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
   bp->sched = sc;
   char buf[200];
   snprintf(buf, sizeof buf,
-           "{\"seg\": %d, \"lds_budget\": %d, \"units\": %d, \"grid\": %d, \"lds\": %d, \"launches\": %d}", sc.seg,
-           sc.budget, units, grid, lds, launches);
+           "{\"seg\": %d, \"lds_budget\": %d, \"units\": %d, \"grid\": %d, \"lds\": %d, \"launches\": %d, "
+           "\"class_segs\": [", sc.seg, sc.budget, units, grid, lds, launches);
   bp->sched_json = buf;
+  for (size_t c = 0; c < sc.class_seg.size(); ++c) bp->sched_json += (c ? ", " : "") + std::to_string(sc.class_seg[c]);
+  bp->sched_json += "]}";
   return AOL_OK;
 }
 
@@ -307,18 +325,31 @@ static std::string batch_key(const aol_batch_plan* bp) {
   return k + buf;
 }
 
-// Tiny line-oriented cache: "key seg budget" per line.
+// Tiny line-oriented cache: "key seg budget n_classes class_seg..." per line
+// (the last line of a key wins).
 static bool cache_lookup(const std::string& path, const std::string& key, Schedule* sc) {
   FILE* f = fopen(path.c_str(), "r");
   if (!f) return false;
-  char line[512];
+  char line[4096];
   bool found = false;
   while (fgets(line, sizeof line, f)) {
     char k[400];
-    int seg = 0, budget = 0;
-    if (sscanf(line, "%399s %d %d", k, &seg, &budget) == 3 && key == k) {
+    int seg = 0, budget = 0, used = 0;
+    if (sscanf(line, "%399s %d %d%n", k, &seg, &budget, &used) == 3 && key == k) {
       sc->seg = seg;
       sc->budget = budget;
+      sc->class_seg.clear();
+      int n = 0, m = 0;
+      const char* rest = line + used;
+      if (sscanf(rest, "%d%n", &n, &m) == 1 && n > 0 && n <= 4096) {
+        rest += m;
+        for (int c = 0; c < n; ++c) {
+          int v = 0;
+          if (sscanf(rest, "%d%n", &v, &m) != 1) break;
+          rest += m;
+          sc->class_seg.push_back(v);
+        }
+      }
       found = true;
     }
   }
@@ -329,7 +360,9 @@ static bool cache_lookup(const std::string& path, const std::string& key, Schedu
 static void cache_store(const std::string& path, const std::string& key, const Schedule& sc) {
   FILE* f = fopen(path.c_str(), "a");
   if (!f) return;
-  fprintf(f, "%s %d %d\n", key.c_str(), sc.seg, sc.budget);
+  fprintf(f, "%s %d %d %d", key.c_str(), sc.seg, sc.budget, (int)sc.class_seg.size());
+  for (int v : sc.class_seg) fprintf(f, " %d", v);
+  fprintf(f, "\n");
   fclose(f);
 }
 
@@ -404,6 +437,22 @@ aol_status aol_batch_plan_create(int32_t n_streams, const aol_stream_desc* strea
     P.split = fb.split;
     P.kmax = std::max(P.kmax, fb.kmax);
     P.ids.push_back(i);
+  }
+  // tuner classes (ratios, width class), ordered by their input bytes
+  {
+    std::vector<StreamClass> cl;
+    bp->cls.resize(n_streams);
+    for (int i = 0; i < n_streams; ++i) {
+      const StreamClass c{bp->hf[i].p, bp->hf[i].q, bp->vf[i].p, bp->vf[i].q, width_class(bp->desc[i].width)};
+      size_t j = 0;
+      while (j < cl.size() && !(cl[j] == c)) ++j;
+      if (j == cl.size()) {
+        cl.push_back(c);
+        bp->cls_bytes.push_back(0);
+      }
+      bp->cls[i] = (int)j;
+      bp->cls_bytes[j] += bp->desc[i].height * bp->desc[i].width;
+    }
   }
   bp->key = batch_key(bp);
   Schedule sc;
@@ -519,6 +568,24 @@ aol_status aol_graph_destroy(aol_graph* graph) {
   return ok();
 }
 
+// Mean time of three launches of a schedule after one warm-up; a negative
+// time when the schedule does not fit.
+static aol_status time_schedule(aol_batch_plan* plan, const Schedule& sc, hipStream_t stream, hipEvent_t e0,
+                                hipEvent_t e1, float* ms) {
+  *ms = -1.f;
+  if (batch_build(plan, sc) != AOL_OK) return AOL_OK;  // candidate does not fit
+  aol_status st = batch_launch(plan, stream);           // warm-up
+  if (st) return st;
+  hipError_t e;
+  if ((e = hipEventRecord(e0, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  for (int r = 0; r < 3 && !st; ++r) st = batch_launch(plan, stream);
+  if (st) return st;
+  if ((e = hipEventRecord(e1, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  if ((e = hipEventElapsedTime(ms, e0, e1)) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+  return AOL_OK;
+}
+
 aol_status aol_autotune(aol_batch_plan* plan, hipStream_t stream) {
   if (!plan) return fail(AOL_ERR_INVALID, "NULL plan");
   if (!plan->pointers_set) return fail(AOL_ERR_INVALID, "aol_autotune needs aol_batch_set_pointers first");
@@ -531,29 +598,46 @@ aol_status aol_autotune(aol_batch_plan* plan, hipStream_t stream) {
   }
   Schedule best = plan->sched;
   float best_ms = 1e30f;
+  aol_status st = AOL_OK;
+  // 1. one segment length and LDS budget (column band) for every stream
   const int segs[] = {16, 32, 64, 128};
   const int budgets[] = {150 * 1024, 76 * 1024};
-  aol_status st = AOL_OK;
   for (int budget : budgets) {
     for (int seg : segs) {
       Schedule sc;
       sc.seg = seg;
       sc.budget = budget;
-      if (batch_build(plan, sc) != AOL_OK) continue;  // candidate does not fit
-      if ((st = batch_launch(plan, stream))) break;   // warm-up
-      if ((e = hipEventRecord(e0, stream)) != hipSuccess) { st = hip_fail(e, "hipEventRecord"); break; }
-      for (int r = 0; r < 3 && !st; ++r) st = batch_launch(plan, stream);
-      if (st) break;
-      if ((e = hipEventRecord(e1, stream)) != hipSuccess) { st = hip_fail(e, "hipEventRecord"); break; }
-      if ((e = hipEventSynchronize(e1)) != hipSuccess) { st = hip_fail(e, "hipEventSynchronize"); break; }
       float ms = 0.f;
-      if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { st = hip_fail(e, "hipEventElapsedTime"); break; }
-      if (ms < best_ms) {
+      if ((st = time_schedule(plan, sc, stream, e0, e1, &ms))) break;
+      if (ms >= 0.f && ms < best_ms) {
         best_ms = ms;
         best = sc;
       }
     }
     if (st) break;
+  }
+  // 2. then each stream class's own segment length, classes with the most
+  // input first, the others held at their best so far (one pass)
+  if (!st && best_ms < 1e30f) {
+    std::vector<int> order(plan->cls_bytes.size());
+    for (size_t c = 0; c < order.size(); ++c) order[c] = (int)c;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return plan->cls_bytes[a] > plan->cls_bytes[b]; });
+    best.class_seg.assign(order.size(), 0);
+    const int class_segs[] = {16, 32, 48, 64, 96, 128};
+    for (int c : order) {
+      for (int seg : class_segs) {
+        Schedule sc = best;
+        sc.class_seg[c] = seg;
+        float ms = 0.f;
+        if ((st = time_schedule(plan, sc, stream, e0, e1, &ms))) break;
+        if (ms >= 0.f && ms < best_ms) {
+          best_ms = ms;
+          best = sc;
+        }
+      }
+      if (st) break;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
