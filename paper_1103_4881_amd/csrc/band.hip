@@ -63,13 +63,19 @@ __device__ __forceinline__ void lds_barrier() {
 
 constexpr int kBandWaves = kBandThreads / 64;
 constexpr int kBandLoadWaves = kBandLoadThreads / 64;
-static_assert(kBandMinHShares == kBandWaves, "every wave takes at least one share of the horizontal pass");
+static_assert(kBandMinHShares == 2 * (kBandWaves - kBandLoadWaves),
+              "the compute waves alone can take every share of the horizontal pass");
 
-// Shares of the horizontal pass each loading wave takes: two where the
-// registers allow (the compute waves also run the vertical pass), else one.
-template <bool SPLIT, int KM, int SLOTS>
+// Shares of the horizontal pass each loading wave takes. None for the
+// integer form with int8 taps and one K-step: there the loading waves' staging
+// writes and loads queue behind each other at the LDS and the address unit
+// right after every barrier, and matrix work behind that queue sets the
+// step's length (measured 1.5-3 % faster without it). Otherwise two where the
+// registers allow (the compute waves also run the vertical pass), else one
+// (measured faster for the float forms and the split taps).
+template <int ELEM, bool SPLIT, int KM, int SLOTS>
 struct BandLoadShares {
-  static constexpr int value = SPLIT || (KM >= 2 && SLOTS >= 4) ? 1 : 2;
+  static constexpr int value = (ELEM == kU8 && !SPLIT && KM == 1) ? 0 : SPLIT || (KM >= 2 && SLOTS >= 4) ? 1 : 2;
 };
 
 // Pointers read from memory (descriptor and pointer tables) are generic to
@@ -285,8 +291,8 @@ struct BandFeed {
 };
 
 // Horizontal pass of one step by one share. The pass is cut into shares:
-// one or two for each loading wave and one for each compute wave (the
-// compute waves also run the vertical pass). Each share takes
+// LS (none, one or two) for each loading wave and one or two for each
+// compute wave (the compute waves also run the vertical pass). Each share takes
 // blocks of one position lb within the period (shares v = lb, lb + nblk,
 // ...: share v handles blocks lb + nblk*(v/nblk + gw*i), gw the shares of
 // position lb), so its coefficient operands and biases are the same for all
@@ -294,13 +300,15 @@ struct BandFeed {
 // staged chunks and ring rows advance by fixed strides. Writes 16
 // intermediate lines of each of its 16-column blocks, transposed, into the
 // ring.
-template <int ELEM, bool SPLIT, int KM, int NB>  // NB: blocks per iteration (operands in flight)
+// NB: blocks per iteration (operands in flight); CACHED: coefficient
+// operands kept in registers where KM allows.
+template <int ELEM, bool SPLIT, int KM, int NB, bool CACHED = true>
 struct BandH {
   static constexpr int ES = ELEM == kU8 ? 1 : 2;
   static constexpr int E = 16 / ES;
   // operands of four K-steps would not fit in registers beside the vertical
   // pass's: read from LDS for every block instead
-  static constexpr bool CACHE = KM <= 2;
+  static constexpr bool CACHE = CACHED && KM <= 2;
   v4i bf[CACHE ? KM : 1], bfh[SPLIT && CACHE ? KM : 1];  // coefficient operands of the wave's position
   const uint8_t* fl;  // lane's slot of the position's first fragment
   const uint8_t* bl;  // lane's bias
@@ -309,7 +317,7 @@ struct BandH {
   const uint8_t* xa;  // lane's A chunk of the wave's first block (staging buffer 0)
   uint8_t* zl;        // lane's ring row of the wave's first block
 
-  // v: this share's index among the nv shares of the pass
+  // v: this share's index among the nv shares of the pass (none if v >= nv)
   __device__ __forceinline__ void setup(const BandStream& S, const BandUnitGeo& G, const uint8_t* lds, int v, int nv,
                                         int lane) {
     const cband_t hb = (cband_t)S.hb;
@@ -322,7 +330,7 @@ struct BandH {
     // in vector registers make the block loop divergent, and a K-step skipped
     // under an EXEC mask is not skipped at all (MFMA ignores EXEC), so the
     // stale operands of an unused K-step would be added in.
-    nbi = __builtin_amdgcn_readfirstlane(b0 < G.nbh ? (G.nbh - b0 + bstep - 1) / bstep : 0);
+    nbi = __builtin_amdgcn_readfirstlane(v < nv && b0 < G.nbh ? (G.nbh - b0 + bstep - 1) / bstep : 0);
     nk = __builtin_amdgcn_readfirstlane(hb->nk[lb]);
     const int fb = hb->frag[lb];
     fl = lds + S.lds_fh + lane * 16 + fb * (SPLIT ? 2048 : 1024);
@@ -547,7 +555,7 @@ struct BandCursor {
 // Loading waves (whole chunks): one pipeline over all the workgroup's units.
 // Each step commits the next step's lines (maybe the next unit's first) into
 // the staging buffer the compute waves are not reading, issues the loads D
-// steps ahead, takes its share of the horizontal pass, and meets the
+// steps ahead, takes its LS shares of the horizontal pass, and meets the
 // compute waves at the step's barrier; a unit adds a barrier at its end (its
 // LDS free) and one at the next unit's start (its coefficients in place).
 // The staging buffer of a step is the parity of its index in the
@@ -572,7 +580,7 @@ __device__ __forceinline__ void band_load_pipeline(const BandLaunch& L, uint8_t*
   int xo[SLOTS];
   BandFeed<ELEM, SLOTS>::offsets(S, tid, xo);
   HP H, H2;  // this wave's shares of the horizontal pass (H2: when LS is 2)
-  H.setup(S, G, lds, wave, NV, lane);
+  if constexpr (LS > 0) H.setup(S, G, lds, wave, NV, lane);
   if constexpr (LS == 2) H2.setup(S, G, lds, wave + kBandLoadWaves, NV, lane);
   v4i pre[D][SLOTS];
 #pragma unroll
@@ -584,7 +592,7 @@ __device__ __forceinline__ void band_load_pipeline(const BandLaunch& L, uint8_t*
   C.issue(pre[0]);
   C.advance(L, tid);
   lds_barrier();  // step 0 staged, the unit's coefficients in place
-  H.load_operands();
+  if constexpr (LS > 0) H.load_operands();
   if constexpr (LS == 2) H2.load_operands();
   int m = 0, t = 0, zm = 0;  // step within the unit, step within the workgroup, ring line
   bool live = true;          // uniform: units left
@@ -604,7 +612,7 @@ __device__ __forceinline__ void band_load_pipeline(const BandLaunch& L, uint8_t*
       C.issue(pre[j]);
       C.advance(L, tid);
       if (live) {
-        H.run(zm, t & 1, g);  // this wave's shares of step m's horizontal pass
+        if constexpr (LS > 0) H.run(zm, t & 1, g);  // this wave's shares of step m's horizontal pass
         if constexpr (LS == 2) H2.run(zm, t & 1, g);
         zm = zm + 16 == S.ring ? 0 : zm + 16;
         lds_barrier();  // step m done with its buffer, the next step staged
@@ -614,12 +622,12 @@ __device__ __forceinline__ void band_load_pipeline(const BandLaunch& L, uint8_t*
           live = i < i1;
           if (live) {
             band_unit<ELEM>(L, band_unit_at(L, i), S, G);
-            H.setup(S, G, lds, wave, NV, lane);
+            if constexpr (LS > 0) H.setup(S, G, lds, wave, NV, lane);
             if constexpr (LS == 2) H2.setup(S, G, lds, wave + kBandLoadWaves, NV, lane);
             m = -1;
             zm = 0;
             lds_barrier();  // the unit's coefficients in place (its step 0 was staged before)
-            H.load_operands();
+            if constexpr (LS > 0) H.load_operands();
             if constexpr (LS == 2) H2.load_operands();
           }
         }
@@ -648,17 +656,17 @@ __device__ __forceinline__ void band_load_gathered(const BandLaunch& L, uint8_t*
     BandFeed<ELEM, SLOTS> F;
     F.setup(S, G, tid);
     HP H, H2;
-    H.setup(S, G, lds, wave, NV, lane);
+    if constexpr (LS > 0) H.setup(S, G, lds, wave, NV, lane);
     if constexpr (LS == 2) H2.setup(S, G, lds, wave + kBandLoadWaves, NV, lane);
     uint8_t* xs = lds + S.lds_x;
     F.stage_gathered(S, G, 0, xs + (t0 & 1) * S.xbuf);
     lds_barrier();  // step 0 staged, the unit's coefficients in place
-    H.load_operands();
+    if constexpr (LS > 0) H.load_operands();
     if constexpr (LS == 2) H2.load_operands();
     int zm = 0;
     for (int m = 0; m < G.M; ++m) {
       if (m + 1 < G.M) F.stage_gathered(S, G, m + 1, xs + ((t0 + m + 1) & 1) * S.xbuf);
-      H.run(zm, (t0 + m) & 1, g);
+      if constexpr (LS > 0) H.run(zm, (t0 + m) & 1, g);
       if constexpr (LS == 2) H2.run(zm, (t0 + m) & 1, g);
       zm = zm + 16 == S.ring ? 0 : zm + 16;
       lds_barrier();  // step m done with its buffer, step m+1 staged
@@ -678,11 +686,11 @@ __device__ __forceinline__ void band_body(const BandLaunch& L, uint8_t* lds) {
   constexpr bool split = (ELEM == kU8) && SPLIT;
   constexpr int NW = (kBandThreads - kBandLoadThreads) / 64;  // compute waves
   constexpr int NB = KM <= 2 && !split ? 4 : 1;               // vertical blocks per iteration (operands in flight)
-  // horizontal blocks per iteration: about two per share and step at the usual ratios
-  constexpr int NBH = NB > 2 ? 2 : NB;
+  constexpr int LS = BandLoadShares<ELEM, split, KM, SLOTS>::value;  // horizontal shares per loading wave
+  // horizontal blocks per iteration: all four where the compute waves take
+  // the whole pass, else about two per share and step at the usual ratios
+  constexpr int NBH = LS == 0 ? NB : (NB > 2 ? 2 : NB);
   constexpr int NBL = 1;  // the loading waves: one (their prefetch holds the registers; measured no slower)
-  constexpr int LS = BandLoadShares<split, KM, SLOTS>::value;  // horizontal shares per loading wave
-  constexpr int NV = LS * kBandLoadWaves + NW;                 // shares of the horizontal pass
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const bool loader = wave < kBandLoadThreads / 64;
@@ -738,10 +746,18 @@ __device__ __forceinline__ void band_body(const BandLaunch& L, uint8_t* lds) {
         reinterpret_cast<v4i*>(zs + S.zhalf)[i] = v4i{0, 0, 0, 0};
       }
     }
-    // this wave's share of the horizontal pass, and the unit's vertical
-    // blocks (lane B: block B)
+    // This wave's shares of the horizontal pass (a share takes blocks of one
+    // position of the period): with loading-wave shares, the last NW of
+    // LS * 8 + NW; without, one per compute wave, two when the filter has
+    // more positions per period than there are compute waves. Then the
+    // unit's vertical blocks (lane B: block B). (The second share is set up
+    // unconditionally, with no blocks when unused: state set on one path
+    // only would lose its uniformity to the compiler.)
+    const int nv = LS > 0 ? LS * kBandLoadWaves + NW : hb->nblk > NW ? 2 * NW : NW;
     BandH<ELEM, split, KM, NBH> H;
-    H.setup(S, G, lds, (LS - 1) * kBandLoadWaves + wave, NV, lane);  // the last shares
+    BandH<ELEM, split, KM, NBH, false> H2;  // (rarely used: operands read from LDS)
+    H.setup(S, G, lds, LS > 0 ? (LS - 1) * kBandLoadWaves + wave : cw, nv, lane);
+    if constexpr (LS == 0) H2.setup(S, G, lds, cw + NW, nv, lane);
     uint32_t vtbl = 0;  // lane B: vertical block B (read after the unit's first barrier)
     int vneed = 0;      // and the intermediate lines its window reaches
     const int vz = vb->zfrag;
@@ -903,6 +919,7 @@ __device__ __forceinline__ void band_body(const BandLaunch& L, uint8_t* lds) {
 
     lds_barrier();  // step 0 staged, coefficients in place
     H.load_operands();
+    if constexpr (LS == 0) H2.load_operands();
     {
       const uint32_t* vt = reinterpret_cast<const uint32_t*>(lds + S.lds_vt);
       vtbl = lane < G.NBV ? vt[lane] : 0u;
@@ -914,7 +931,8 @@ __device__ __forceinline__ void band_body(const BandLaunch& L, uint8_t* lds) {
       // vertical blocks complete with step m-1's lines (the horizontal pass of
       // step m writes other ring lines meanwhile)
       vpass(min(G.Lz, 16 * m));
-      H.run(zm, (t0 + m) & 1, g);  // this wave's share of step m's horizontal pass
+      H.run(zm, (t0 + m) & 1, g);  // this wave's shares of step m's horizontal pass
+      if constexpr (LS == 0) H2.run(zm, (t0 + m) & 1, g);
       zm = zm + 16 == S.ring ? 0 : zm + 16;
       lds_barrier();  // step m's intermediate lines written, step m+1 staged
     }
