@@ -43,6 +43,49 @@ struct LinearArgs {
   int32_t t_ifd, t_w, t_bias, t_ooff, t_ofd;  // offsets (int32 entries) of the table's parts
 };
 
+// Staged form: a workgroup takes C = kLinThreads * ppt consecutive points of
+// one row of the repetition space (every index but the last fixed). Where
+// consecutive points advance both arrays by constant flat strides P and Po,
+// the input bytes the chunk's points read lie in a few contiguous ranges (one
+// per group of pattern elements whose offsets are close): those are loaded
+// into LDS with 16-byte loads, and the points read their pattern from there.
+// Output elements grouped in runs of Po consecutive offsets cover their
+// ranges densely: the points write into LDS and the workgroup stores whole
+// 16-byte chunks. Points whose pattern crosses an array border (or whose
+// coordinates wrap inside the chunk) take the point-by-point path. LDS holds
+// first, per chunk, each element's position relative to a point's flat
+// position (4 * (2 n_pairs + NOUT) bytes, rounded to 16), then the groups.
+constexpr int kLinGroups = 4;          // input / output element groups at most
+constexpr int kLinStageLds = 40 * 1024;  // LDS bytes of a staged workgroup at most
+constexpr int kLinStageMaxIn = 32;       // input pattern elements of a staged plan at most
+constexpr int64_t kLinCoordTable = 1 << 22;  // table entries (int32) of a staged plan at most
+
+struct LinearStage {
+  int32_t ppt;             // points per thread (0: staged form not used)
+  int32_t chunks;          // workgroups per row
+  int32_t P, Po;           // flat strides between consecutive points (input, output), > 0
+  int32_t ng, ngo;         // input groups; dense output groups (0: outputs stored point by point)
+  int32_t gb[kLinGroups];  // input group: least flat offset of its elements
+  int32_t gs[kLinGroups];  // input group: extent of its offsets (largest - least + 1)
+  int32_t gl[kLinGroups];  // input group: LDS byte base
+  int32_t ob[kLinGroups];  // output group: least flat offset (its elements are ob .. ob + Po - 1)
+  int32_t ol[kLinGroups];  // output group: LDS byte base
+  int32_t lds_bytes;
+  // table offsets: group of each input element (2 n_pairs), of each output
+  // element (NOUT), and per group (kLinGroups) gb, gl, ob, ol
+  int32_t t_eg, t_og, t_grp;
+  int64_t n_in, n_out;     // elements of the input and output arrays
+  // Wrapped coordinates of a chunk's first point without 64-bit division:
+  // for array dim dd (input dims, then output dims) the table at
+  // cq + dd * cq_len holds, for rep dim k < last, (P[.][k] * r) mod S at
+  // cq_k[k] + r (r < R[k]), and for the last dim (P[.][last] * x0) mod S of
+  // each chunk's first point x0 at cq_k[last] + chunk.
+  int32_t cq, cq_len;
+  int32_t cq_k[kLinRank];
+  uint32_t mg_R[kLinRank];  // floor(2^32 / R[k]) + 1, and of chunks at [last]
+};
+
 hipError_t linear_launch(int nout, const LinearArgs& a, hipStream_t stream);
+hipError_t linear_staged_launch(int nout, const LinearArgs& a, const LinearStage& st, hipStream_t stream);
 
 }  // namespace aol

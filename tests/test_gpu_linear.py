@@ -3,8 +3,9 @@
 Workloads: interleaved RGB to planar colour components and the composition back, both with
 frames as a repetition dimension; non-separable 2-D polyphase filters with p x p outputs per
 repetition; random tilers (strided, transposed and wrapping fittings) with random weights; a
-multi-element interleaving output tiler. Outputs are pre-filled with 0x00 and 0xFF: both runs must
-agree (every element written once).
+multi-element interleaving output tiler. Every case runs on 16-byte aligned arrays (the staged form
+where it applies) and on views one byte off (point by point); outputs are pre-filled with 0x00 and
+0xFF: all four runs must agree (every element written once) and leave guard bytes untouched.
 """
 
 import numpy as np
@@ -30,16 +31,27 @@ def _at(spec, rep):
 
 
 def _run(X, tin, tout, rep, W, bias):
+    """Both forms of the kernel: 16-byte aligned arrays (the staged form wherever the tilers allow
+    it) and views one byte off alignment (point by point), each with two sentinel fills and guard
+    bytes around the output that must stay untouched."""
     plan = aol.LinearPlan(_at(tin, rep), _at(tout, rep), W, bias)
-    x = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    shape = tuple(tout.array_shape)
+    n_in, n_out = int(X.size), int(np.prod(shape))
     outs = []
-    for fill in (0x00, 0xFF):
-        y = torch.full(tuple(tout.array_shape), fill, dtype=torch.uint8, device="cuda")
-        plan.run(x, y)
-        torch.cuda.synchronize()
-        outs.append(y.cpu().numpy())
+    for off in (0, 1):
+        xb = torch.empty(n_in + 32, dtype=torch.uint8, device="cuda")
+        x = xb[off:off + n_in].view(X.shape)
+        x.copy_(torch.from_numpy(np.ascontiguousarray(X)))
+        for fill in (0x00, 0xFF):
+            yb = torch.full((n_out + 32,), fill, dtype=torch.uint8, device="cuda")
+            plan.run(x, yb[off:off + n_out].view(shape))
+            torch.cuda.synchronize()
+            h = yb.cpu().numpy()
+            assert (h[:off] == fill).all() and (h[off + n_out:] == fill).all(), "write outside the output"
+            outs.append(h[off:off + n_out].reshape(shape))
     plan.close()
-    np.testing.assert_array_equal(outs[0], outs[1], err_msg="outputs differ between sentinel fills")
+    for k in range(1, len(outs)):
+        np.testing.assert_array_equal(outs[0], outs[k], err_msg=f"outputs differ between forms / fills ({k})")
     return outs[0]
 
 
@@ -126,6 +138,33 @@ def test_interleaving_output_pattern_and_wrapping_input():
     W = g.integers(-100, 200, size=(2, 15)).astype(np.int16)
     Y = _run(X, tin, tout, (h, w), W, np.array([300, -700], np.int32))
     np.testing.assert_array_equal(Y, _oracle(X, tin, tout, (h, w), W, np.array([300, -700])))
+
+
+@pytest.mark.parametrize("h,w", [(5, 3001), (2, 2049), (3, 4096)])
+def test_rgb_rows_of_several_chunks(h, w):
+    """Rows longer than one staged chunk (2048 points): whole chunks, a partial last chunk."""
+    X = synthgen.uniform_frame(h + w, h, 3 * w)
+    rep, tin, tout = synthgen.rgb_to_planar_tilers(h, w)
+    Y = _run(X, tin, tout, rep, synthgen.RGB_TO_YCC_W, synthgen.RGB_TO_YCC_BIAS)
+    np.testing.assert_array_equal(Y, _oracle(X, tin, tout, rep, synthgen.RGB_TO_YCC_W, synthgen.RGB_TO_YCC_BIAS))
+    rep2, tin2, tout2 = synthgen.planar_to_rgb_tilers(h, w)
+    Z = _run(Y, tin2, tout2, rep2, synthgen.YCC_TO_RGB_W, synthgen.YCC_TO_RGB_BIAS)
+    np.testing.assert_array_equal(Z, _oracle(Y, tin2, tout2, rep2, synthgen.YCC_TO_RGB_W, synthgen.YCC_TO_RGB_BIAS))
+
+
+def test_wide_wrapping_pattern_mixes_clean_and_border_chunks():
+    """A 5 x 3 pattern wrapping both borders on rows of 5000 points: the chunks at a row's ends
+    cross a border (point by point), the middle ones do not (staged), rows at the top and bottom
+    wrap vertically."""
+    h, w = 9, 5000
+    X = synthgen.uniform_frame(43, h, w)
+    tin = synthgen.TilerSpec((h, w), (-2, -1), [[1, 0], [0, 1]], [[1, 0], [0, 1]], (5, 3))
+    tout = synthgen.TilerSpec((h, 2 * w), (0, 0), [[1, 0], [0, 2]], [[0], [1]], (2,))
+    g = synthgen.rng_for(44, 0)
+    W = g.integers(-100, 200, size=(2, 15)).astype(np.int16)
+    bias = np.array([-300, 900], np.int32)
+    Y = _run(X, tin, tout, (h, w), W, bias)
+    np.testing.assert_array_equal(Y, _oracle(X, tin, tout, (h, w), W, bias))
 
 
 def test_errors():
