@@ -424,7 +424,10 @@ typedef struct aol_linear_plan aol_linear_plan;
 aol_status aol_linear_plan_create(const aol_tiler* in, const aol_tiler* out, const int16_t* weights,
                                   const int32_t* bias, aol_linear_plan** plan);
 /* d_in: prod(in->array_shape) bytes; d_out: prod(out->array_shape) bytes; must
- * not alias. Enqueue only. */
+ * not alias. Any alignment; with both pointers 16-byte aligned, plans with
+ * small patterns (at most 32 input elements, positive strides between
+ * consecutive points of the last repetition dim) stage their rows through
+ * LDS with 16-byte accesses (same results). Enqueue only. */
 aol_status aol_linear_run(aol_linear_plan* plan, const uint8_t* d_in, uint8_t* d_out, hipStream_t stream);
 aol_status aol_linear_plan_destroy(aol_linear_plan* plan);
 
