@@ -327,30 +327,42 @@ aol_status aol_linear_plan_create(const aol_tiler* in, const aol_tiler* out, con
         tab.push_back(g < st.ngo ? st.ob[g] : 0);
         tab.push_back(g < st.ngo ? st.ol[g] : 0);
       }
-      // coordinate tables (see LinearStage)
+      // per-chunk clean test and first positions (see LinearStage)
       const int last = a.rr - 1;
-      int64_t len = 0;
-      for (int k = 0; k < last; ++k) {
-        st.cq_k[k] = (int32_t)len;
-        len += a.R[k];
-      }
-      st.cq_k[last] = (int32_t)len;
-      len += st.chunks;
-      const int ndim = a.ra + a.ro;
-      if (len * ndim + (int64_t)tab.size() > kLinCoordTable) {
+      const int64_t rows = a.nrep / a.R[last];
+      const int64_t nchunks = rows * st.chunks;
+      if (2 * nchunks + (int64_t)tab.size() > kLinCoordTable) {
         st.ppt = 0;  // too large: point by point
       } else {
         st.cq = (int32_t)tab.size();
-        st.cq_len = (int32_t)len;
-        const int64_t C = (int64_t)kLinThreads * st.ppt;
-        for (int dd = 0; dd < ndim; ++dd) {
-          const bool isin = dd < a.ra;
-          const int d = isin ? dd : dd - a.ra;
-          const int64_t S = isin ? a.S[d] : a.So[d];
-          for (int k = 0; k <= last; ++k) {
-            const int64_t P = isin ? a.P[d][k] : a.Po[d][k];
-            const int64_t n = k < last ? a.R[k] : st.chunks;
-            for (int64_t v = 0; v < n; ++v) tab.push_back((int32_t)((P * (k < last ? v : v * C)) % S));
+        const int C = kLinThreads * st.ppt;
+        int64_t r[kLinRank] = {0, 0, 0, 0};
+        for (int64_t row = 0; row < rows; ++row) {
+          for (int c = 0; c < st.chunks; ++c) {
+            const int64_t x0 = (int64_t)c * C, npts = std::min<int64_t>(C, a.R[last] - x0);
+            r[last] = x0;
+            bool clean = true;
+            int64_t flat0 = 0, oflat0 = 0;
+            for (int d = 0; d < a.ra; ++d) {
+              int64_t v = a.o[d];
+              for (int k = 0; k < a.rr; ++k) v += (int64_t)a.P[d][k] * r[k];
+              const int64_t b = v % a.S[d];
+              clean = clean && b + a.lo[d] >= 0 && b + (npts - 1) * a.P[d][last] + a.hi[d] < a.S[d];
+              flat0 += b * a.st[d];
+            }
+            for (int d = 0; d < a.ro; ++d) {
+              int64_t v = a.oo[d];
+              for (int k = 0; k < a.rr; ++k) v += (int64_t)a.Po[d][k] * r[k];
+              const int64_t b = v % a.So[d];
+              clean = clean && b + a.olo[d] >= 0 && b + (npts - 1) * a.Po[d][last] + a.ohi[d] < a.So[d];
+              oflat0 += b * a.sto[d];
+            }
+            tab.push_back(clean ? (int32_t)flat0 : -1);
+            tab.push_back(clean ? (int32_t)oflat0 : -1);
+          }
+          for (int k = last - 1; k >= 0; --k) {  // next row, row-major
+            if (++r[k] < a.R[k]) break;
+            r[k] = 0;
           }
         }
         for (int k = 0; k < last; ++k) st.mg_R[k] = magic((uint32_t)a.R[k]);

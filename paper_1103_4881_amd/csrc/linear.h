@@ -75,13 +75,11 @@ struct LinearStage {
   // element (NOUT), and per group (kLinGroups) gb, gl, ob, ol
   int32_t t_eg, t_og, t_grp;
   int64_t n_in, n_out;     // elements of the input and output arrays
-  // Wrapped coordinates of a chunk's first point without 64-bit division:
-  // for array dim dd (input dims, then output dims) the table at
-  // cq + dd * cq_len holds, for rep dim k < last, (P[.][k] * r) mod S at
-  // cq_k[k] + r (r < R[k]), and for the last dim (P[.][last] * x0) mod S of
-  // each chunk's first point x0 at cq_k[last] + chunk.
-  int32_t cq, cq_len;
-  int32_t cq_k[kLinRank];
+  // Per chunk (workgroup) g, at cq + 2 g: the flat input and output
+  // positions of its first point, or -1 when the chunk is not clean (some
+  // point's pattern crosses an array border, or a coordinate wraps between
+  // the chunk's first and last point), computed on the host.
+  int32_t cq;
   uint32_t mg_R[kLinRank];  // floor(2^32 / R[k]) + 1, and of chunks at [last]
 };
 

@@ -210,8 +210,13 @@ __global__ __launch_bounds__(kLinThreads) void k_linear_staged(LinearArgs a, Lin
   const int C = kLinThreads * st.ppt;
   const int x0 = chunk * C;
   const int npts = min(C, a.R[last] - x0);  // uniform, >= 1
-  int r[kLinRank] = {0, 0, 0, 0};
-  {
+  const ctab_t tab = (ctab_t)a.tab;
+  // the chunk's flat input and output positions of its first point, or -1:
+  // not clean (computed on the host)
+  const int flat0 = tab[st.cq + 2 * blockIdx.x], oflat0 = tab[st.cq + 2 * blockIdx.x + 1];
+  const bool clean = flat0 >= 0;
+  if (!clean) {  // uniform
+    int r[kLinRank] = {0, 0, 0, 0};
     uint32_t row = rowi;
 #pragma unroll
     for (int k = kLinRank - 1; k >= 0; --k) {
@@ -221,40 +226,6 @@ __global__ __launch_bounds__(kLinThreads) void k_linear_staged(LinearArgs a, Lin
         row = q;
       }
     }
-  }
-  const ctab_t tab = (ctab_t)a.tab;
-  // wrapped coordinate along array dim dd of the chunk's first point: the
-  // origin plus one reduced term per repetition dim, each add wrapped once
-  auto coord = [&](int dd, int o, int S) {
-    const ctab_t t = tab + st.cq + dd * st.cq_len;
-    int c = o;
-#pragma unroll
-    for (int k = 0; k < kLinRank; ++k) {
-      if (k <= last) {
-        c += t[st.cq_k[k] + (k == last ? chunk : r[k])];
-        if (c >= S) c -= S;
-      }
-    }
-    return c;
-  };
-  // the clean test: every point's pattern inside both arrays, no coordinate
-  // wrapping between the chunk's first and last point
-  bool clean = true;
-  int flat0 = 0, oflat0 = 0;
-#pragma unroll
-  for (int d = 0; d < kLinRank; ++d) {
-    if (d < a.ra) {
-      const int b = coord(d, a.o[d], a.S[d]);
-      clean = clean && b + a.lo[d] >= 0 && (int64_t)b + (int64_t)(npts - 1) * a.P[d][last] + a.hi[d] < a.S[d];
-      flat0 += b * a.st[d];
-    }
-    if (d < a.ro) {
-      const int ob = coord(a.ra + d, a.oo[d], a.So[d]);
-      clean = clean && ob + a.olo[d] >= 0 && (int64_t)ob + (int64_t)(npts - 1) * a.Po[d][last] + a.ohi[d] < a.So[d];
-      oflat0 += ob * a.sto[d];
-    }
-  }
-  if (!clean) {  // uniform
     linear_points<NOUT>(a, r, x0, x0 + npts);
     return;
   }
