@@ -131,6 +131,23 @@ def test_sixteen_blocks_per_period(p, q, T):
     np.testing.assert_array_equal(Y, pp.downscale_u8(X, of, of))
 
 
+@pytest.mark.parametrize("p,q", [(9, 16), (12, 16), (16, 24)])
+def test_many_block_positions_with_int8_taps(p, q):
+    """More block positions per period than compute waves (p > 8) with taps that fit int8 and
+    one K-step: the loading waves take no share of the horizontal pass and each compute wave
+    takes two (the second reading its coefficient operands from LDS)."""
+    T = 8
+    c = np.full((p, T), 32)  # each phase sums to 256, every tap within int8
+    hf, of = aol.Polyphase(p, q, c), pp.Filter(p, q, c)
+    plan = aol.DownscalePlan([(140, 416)], hf, hf, "u8")
+    sched = plan.schedule(2)
+    plan.close()
+    assert sched["kernel"] == "band" and sched["split"] == 0 and sched["kmax"] == 1, sched
+    X = np.stack([synthgen.uniform_frame(19 + p + f, 140, 416, idx=4) for f in range(2)])
+    (Y,) = _run_u8([X], hf, hf)
+    np.testing.assert_array_equal(Y, pp.downscale_u8(X, of, of))
+
+
 def test_two_kstep_filters_many_units_per_workgroup():
     # 3/8 with 16 taps: blocks with one and with two K-steps, column bands, several
     # units per workgroup (a regression: an unused K-step was accumulated)
