@@ -167,6 +167,19 @@ def test_wide_wrapping_pattern_mixes_clean_and_border_chunks():
     np.testing.assert_array_equal(Y, _oracle(X, tin, tout, (h, w), W, bias))
 
 
+def test_outputs_interleaved_by_two_repetitions():
+    """Repetition space (2, h, w): both k = 0 and k = 1 read in[y][x - 1 .. x + 1] and write
+    out[y][2 x + k], so a row's outputs lie two elements apart (no dense output range: clean chunks
+    store point by point from registers; rows of three chunks, the middle one clean)."""
+    h, w = 11, 5000
+    X = synthgen.uniform_frame(45, h, w)
+    tin = synthgen.TilerSpec((h, w), (0, -1), [[0, 1, 0], [0, 0, 1]], [[0], [1]], (3,))
+    tout = synthgen.TilerSpec((h, 2 * w), (0, 0), [[0, 1, 0], [1, 0, 2]], [[], []], ())
+    W = np.array([[60, 120, 76]], np.int16)
+    Y = _run(X, tin, tout, (2, h, w), W, np.array([-50], np.int32))
+    np.testing.assert_array_equal(Y, _oracle(X, tin, tout, (2, h, w), W, np.array([-50])))
+
+
 def test_errors():
     h, w = 4, 5
     rep, tin, tout = synthgen.rgb_to_planar_tilers(h, w)
