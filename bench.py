@@ -431,15 +431,15 @@ def bench_batch(fmt="u8", steps=BATCH_FRAMES, warmup=BATCH_FRAMES, only_size=Non
     with torch.cuda.stream(s):
         plan.set_pointers([ins[i][0] for i in range(len(mix))], [outs[i][0] for i in range(len(mix))], s)
         plan.autotune(s)
-        graph = plan.graph(s)
 
-        # pointer arrays of every frame, checked once (a serving loop keeps them the same way)
-        tables = [plan.pointer_arrays([ins[i][k] for i in range(len(mix))], [outs[i][k] for i in range(len(mix))])
+        # one graph per frame slot, each with its own pointer table (a serving
+        # loop over a ring of frame buffers keeps them the same way): one graph launch per step
+        graphs = [plan.graph_with_pointers(plan.pointer_arrays([ins[i][k] for i in range(len(mix))],
+                                                               [outs[i][k] for i in range(len(mix))]), s)
                   for k in range(BATCH_FRAMES)]
 
         def step(k):
-            plan.set_pointer_arrays(tables[k % BATCH_FRAMES], s)
-            aol.aol_graph_launch(graph, s)
+            aol.aol_graph_launch(graphs[k % BATCH_FRAMES], s)
 
         warm(lambda: step(0), warmup, s.synchronize)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]

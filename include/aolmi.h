@@ -315,6 +315,16 @@ aol_status aol_batch_run(aol_batch_plan* plan, hipStream_t stream);
  * the launch: aol_graph_launch returns AOL_ERR_INVALID for a graph captured
  * before it (capture again), and for a graph whose plan was destroyed. */
 aol_status aol_batch_graph_create(aol_batch_plan* plan, hipStream_t stream, aol_graph** out);
+
+/* Capture one step on a fixed buffer set (d_in[i] / d_out[i], checked as by
+ * aol_batch_set_pointers) into a graph that holds its own pointer table
+ * (allocated and filled here; the plan's table is not touched): a serving
+ * loop over a ring of frame slots keeps one graph per slot and launches one
+ * graph, one kernel, per step. The buffers must stay valid while the graph
+ * is used. The same rules as aol_batch_graph_create apply (non-default
+ * stream; invalid after aol_autotune or the plan's destruction). */
+aol_status aol_batch_graph_create_pointers(aol_batch_plan* plan, const void* const* d_in, void* const* d_out,
+                                           hipStream_t stream, aol_graph** out);
 aol_status aol_graph_launch(aol_graph* graph, hipStream_t stream);
 aol_status aol_graph_destroy(aol_graph* graph);
 

@@ -125,6 +125,8 @@ _proto("aol_batch_set_pointers", ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(c
        ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p)
 _proto("aol_batch_run", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
 _proto("aol_batch_graph_create", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p))
+_proto("aol_batch_graph_create_pointers", ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+       ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p))
 _proto("aol_graph_launch", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
 _proto("aol_graph_destroy", ctypes.c_int, ctypes.c_void_p)
 _proto("aol_autotune", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
@@ -600,6 +602,12 @@ def aol_batch_graph_create(plan, stream):
     return g
 
 
+def aol_batch_graph_create_pointers(plan, d_in, d_out, stream):
+    g = ctypes.c_void_p()
+    _check(_lib.aol_batch_graph_create_pointers(plan, d_in, d_out, _stream_handle(stream), ctypes.byref(g)))
+    return g
+
+
 def aol_graph_launch(graph, stream=None):
     _check(_lib.aol_graph_launch(graph, _stream_handle(stream)))
 
@@ -661,6 +669,13 @@ class BatchPlan:
 
     def graph(self, stream):
         g = aol_batch_graph_create(self._h, stream)
+        self._graphs.append(g)
+        return g
+
+    def graph_with_pointers(self, arrays, stream):
+        """A graph that runs one step on the buffers of `pointer_arrays`, with its own pointer
+        table (one graph per buffer set; the tensors must stay alive)."""
+        g = aol_batch_graph_create_pointers(self._h, arrays[0], arrays[1], stream)
         self._graphs.append(g)
         return g
 

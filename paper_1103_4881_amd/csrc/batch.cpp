@@ -92,6 +92,7 @@ struct aol_batch_plan {
 struct aol_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  DeviceBuf d_ptrs;  // a buffer-set graph's own pointer table (in, out per stream)
   std::shared_ptr<uint64_t> plan_generation;
   uint64_t captured = 0;
 };
@@ -262,7 +263,8 @@ static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
   return AOL_OK;
 }
 
-static BandLaunch part_launch(const aol_batch_plan* bp, const aol_batch_plan::Part& P) {
+// table: the pointer table the launch reads (NULL: the plan's)
+static BandLaunch part_launch(const aol_batch_plan* bp, const aol_batch_plan::Part& P, const void* table = nullptr) {
   BandLaunch L;
   memset(&L, 0, sizeof L);
   L.streams = (const BandStream*)bp->d_streams.ptr;
@@ -271,24 +273,41 @@ static BandLaunch part_launch(const aol_batch_plan* bp, const aol_batch_plan::Pa
   L.n_frames = 1;
   L.total_units = (int32_t)P.units.size();
   L.aligned = 1;  // checked by aol_batch_set_pointers
-  L.ptr_table = (void* const*)bp->d_table.ptr;
+  L.ptr_table = (void* const*)(table ? table : bp->d_table.ptr);
   L.order = (const int32_t*)P.d_order.ptr;
   L.first = (const int32_t*)P.d_first.ptr;
   return L;
 }
 
-static aol_status batch_launch(aol_batch_plan* bp, hipStream_t stream) {
+static aol_status batch_launch(aol_batch_plan* bp, hipStream_t stream, const void* table = nullptr) {
   if (bp->dual) {
     const aol_batch_plan::Part &A = bp->parts[0], &B = bp->parts[1];
-    hipError_t e = band_dual_launch(A.slots, B.slots, std::max(A.kmax, B.kmax), part_launch(bp, A), A.grid,
-                                    part_launch(bp, B), B.grid, bp->dual_lds, stream);
+    hipError_t e = band_dual_launch(A.slots, B.slots, std::max(A.kmax, B.kmax), part_launch(bp, A, table), A.grid,
+                                    part_launch(bp, B, table), B.grid, bp->dual_lds, stream);
     if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
     return AOL_OK;
   }
   for (const aol_batch_plan::Part& P : bp->parts) {
     if (P.ids.empty()) continue;
-    hipError_t e = band_launch(bp->elem, P.slots, P.split, P.kmax, P.gather, part_launch(bp, P), P.grid, P.lds, stream);
+    hipError_t e =
+        band_launch(bp->elem, P.slots, P.split, P.kmax, P.gather, part_launch(bp, P, table), P.grid, P.lds, stream);
     if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+  }
+  return AOL_OK;
+}
+
+// Checks one buffer set (non-NULL, 16-byte aligned) and lays it out as the
+// device pointer table holds it: [in_0, out_0, in_1, out_1, ...].
+static aol_status batch_pointer_list(const aol_batch_plan* plan, const void* const* d_in, void* const* d_out,
+                                     std::vector<const void*>& ptrs) {
+  if (!d_in || !d_out) return fail(AOL_ERR_INVALID, "NULL pointer array");
+  ptrs.assign(2 * (size_t)plan->n, nullptr);
+  for (int i = 0; i < plan->n; ++i) {
+    if (!d_in[i] || !d_out[i]) return fail(AOL_ERR_INVALID, "stream %d: NULL buffer", i);
+    if ((uintptr_t)d_in[i] % 16 || (uintptr_t)d_out[i] % 16)
+      return fail(AOL_ERR_INVALID, "stream %d: batch buffers must be 16-byte aligned", i);
+    ptrs[2 * i] = d_in[i];
+    ptrs[2 * i + 1] = d_out[i];
   }
   return AOL_OK;
 }
@@ -496,15 +515,8 @@ aol_status aol_batch_plan_destroy(aol_batch_plan* plan) {
 aol_status aol_batch_set_pointers(aol_batch_plan* plan, const void* const* d_in, void* const* d_out,
                                   hipStream_t stream) {
   if (!plan) return fail(AOL_ERR_INVALID, "NULL plan");
-  if (!d_in || !d_out) return fail(AOL_ERR_INVALID, "NULL pointer array");
-  std::vector<const void*> ptrs(2 * (size_t)plan->n);
-  for (int i = 0; i < plan->n; ++i) {
-    if (!d_in[i] || !d_out[i]) return fail(AOL_ERR_INVALID, "stream %d: NULL buffer", i);
-    if ((uintptr_t)d_in[i] % 16 || (uintptr_t)d_out[i] % 16)
-      return fail(AOL_ERR_INVALID, "stream %d: batch buffers must be 16-byte aligned", i);
-    ptrs[2 * i] = d_in[i];
-    ptrs[2 * i + 1] = d_out[i];
-  }
+  std::vector<const void*> ptrs;
+  if (aol_status st = batch_pointer_list(plan, d_in, d_out, ptrs)) return st;
   hipError_t e = set_pointers_launch((void**)plan->d_table.ptr, ptrs.data(), 2 * plan->n, stream);
   if (e != hipSuccess) return hip_fail(e, "pointer table update");
   plan->pointers_set = true;
@@ -518,18 +530,27 @@ aol_status aol_batch_run(aol_batch_plan* plan, hipStream_t stream) {
   return st ? st : ok();
 }
 
-aol_status aol_batch_graph_create(aol_batch_plan* plan, hipStream_t stream, aol_graph** out) {
-  if (!plan || !out) return fail(AOL_ERR_INVALID, "NULL argument");
-  *out = nullptr;
+}  // extern "C"
+
+// Captures one batch launch into a graph; with `ptrs` the graph gets its own
+// pointer table holding them (filled now), which its launch reads.
+static aol_status batch_graph_capture(aol_batch_plan* plan, const std::vector<const void*>* ptrs, hipStream_t stream,
+                                      aol_graph** out) {
   if (!stream) return fail(AOL_ERR_INVALID, "graph capture needs a non-default stream");
   aol_graph* g = new (std::nothrow) aol_graph();
   if (!g) return fail(AOL_ERR_NOMEM, "graph allocation");
+  if (ptrs) {
+    if (aol_status st = g->d_ptrs.upload(ptrs->data(), ptrs->size() * sizeof(void*))) {
+      delete g;
+      return st;
+    }
+  }
   hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) {
     delete g;
     return hip_fail(e, "hipStreamBeginCapture");
   }
-  aol_status st = batch_launch(plan, stream);
+  aol_status st = batch_launch(plan, stream, ptrs ? g->d_ptrs.ptr : nullptr);
   e = hipStreamEndCapture(stream, &g->graph);
   if (st || e != hipSuccess) {
     if (g->graph) (void)hipGraphDestroy(g->graph);
@@ -545,7 +566,26 @@ aol_status aol_batch_graph_create(aol_batch_plan* plan, hipStream_t stream, aol_
   g->plan_generation = plan->generation;
   g->captured = *plan->generation;
   *out = g;
-  return ok();
+  return AOL_OK;
+}
+
+extern "C" {
+
+aol_status aol_batch_graph_create(aol_batch_plan* plan, hipStream_t stream, aol_graph** out) {
+  if (!plan || !out) return fail(AOL_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  aol_status st = batch_graph_capture(plan, nullptr, stream, out);
+  return st ? st : ok();
+}
+
+aol_status aol_batch_graph_create_pointers(aol_batch_plan* plan, const void* const* d_in, void* const* d_out,
+                                           hipStream_t stream, aol_graph** out) {
+  if (!plan || !out) return fail(AOL_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  std::vector<const void*> ptrs;
+  aol_status st = batch_pointer_list(plan, d_in, d_out, ptrs);
+  if (!st) st = batch_graph_capture(plan, &ptrs, stream, out);
+  return st ? st : ok();
 }
 
 aol_status aol_graph_launch(aol_graph* graph, hipStream_t stream) {

@@ -78,6 +78,33 @@ def test_batch_u8_run_and_graph_bit_exact(fill):
 
 
 @pytest.mark.parametrize("fill", FILLS)
+def test_batch_graphs_with_pointers_per_frame_slot(fill):
+    """One graph per frame slot, each with its own pointer table: replayed in turn
+    and out of order, with eager work between replays; every output against the oracle."""
+    st = _streams(MIX, seed=5)
+    plan = aol.BatchPlan([(h, w, hf, vf) for (h, w, hf, vf, _, _) in st], "u8")
+    slots = 3
+    frames = _frames(MIX, slots, 13)
+    ins = [[torch.from_numpy(fr).cuda() for fr in fs] for fs in frames]
+    outs = [[torch.full(plan.out_shapes[i], fill, dtype=torch.uint8, device="cuda") for _ in range(slots)]
+            for i in range(len(st))]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        graphs = [plan.graph_with_pointers(plan.pointer_arrays([ins[i][k] for i in range(len(st))],
+                                                               [outs[i][k] for i in range(len(st))]), s)
+                  for k in range(slots)]
+        for rep, k in enumerate([0, 1, 2, 1, 0, 2]):
+            for i in range(len(st)):
+                outs[i][k].fill_(fill)  # eager work between the replays; the replay rewrites the slot
+            aol.aol_graph_launch(graphs[k], s)
+            s.synchronize()
+            for i, (h, w, hf, vf, of, ov) in enumerate(st):
+                np.testing.assert_array_equal(outs[i][k].cpu().numpy(), pp.downscale_u8(frames[i][k], of, ov),
+                                              err_msg=f"replay {rep} slot {k} stream {i}")
+    plan.close()
+
+
+@pytest.mark.parametrize("fill", FILLS)
 def test_batch_autotune_keeps_results(tmp_path, fill):
     st = _streams(MIX[:4], seed=3)
     cache = str(tmp_path / "tune.txt")
