@@ -367,12 +367,17 @@ __global__ __launch_bounds__(256) void k_wsum(WsumArgs a) {
     uint32_t rowbase = 0;
     for (int k = 0; k < a.rr; ++k)
       if (k != a.k_lane && k != a.k_loop) rowbase += (uint32_t)r[k] * (uint32_t)a.ostr_rep[k];
-    const int rl = bp * BJ + lane;
+    // A row of the tile is BJ points: with BJ = 32 the two halves of a wave
+    // take rows r and r + 32 (33 * 32 = 32 mod 64 banks apart: no conflict).
+    constexpr int HALVES = 64 / BJ;
+    const int col = lane % BJ, half = lane / BJ;
+    const int rl = bp * BJ + col;
     const uint32_t sl = (uint32_t)a.ostr_rep[a.k_lane];
-    uint32_t of = rowbase + (uint32_t)(bl * 64 + wave) * sl + (uint32_t)rl * (uint32_t)a.ostr_rep[a.k_loop];
-    const bool col_ok = lane < BJ && rl < a.R[a.k_loop];
-    for (int row = wave; row < 64; row += 4, of += 4 * sl) {
-      if (col_ok && bl * 64 + row < a.R[a.k_lane]) ((gout_t)a.out)[of] = tile[row][lane];
+    const int row0 = wave + half * 32;
+    uint32_t of = rowbase + (uint32_t)(bl * 64 + row0) * sl + (uint32_t)rl * (uint32_t)a.ostr_rep[a.k_loop];
+    const bool col_ok = rl < a.R[a.k_loop];
+    for (int row = row0; row < row0 + 64 / HALVES; row += 4, of += 4 * sl) {
+      if (col_ok && bl * 64 + row < a.R[a.k_lane]) ((gout_t)a.out)[of] = tile[row][col];
     }
   }
 }
