@@ -91,9 +91,10 @@ struct FusedArgs {
 constexpr int kBandThreads = 1024;     // threads of a band-kernel workgroup (16 waves)
 constexpr int kBandLoadThreads = 512;  // waves 0-7 stream input lines into LDS, waves 8-15 compute
 constexpr int kBandMaxSlots = 8;       // 16-byte chunks per loading lane and staged step
-// The horizontal pass is cut into at least one share per wave, each taking
-// one block position of the 16-repetition period, so a filter with more
-// positions (p > 16) does not use the band kernel.
+// The horizontal pass is cut into at least 16 shares (one or two per compute
+// wave, and the loading waves' where they take shares), each taking one block
+// position of the 16-repetition period, so a filter with more positions
+// (p > 16) does not use the band kernel.
 constexpr int kBandMinHShares = 16;
 
 // One plane or video stream of the band kernel (device resident). A

@@ -555,9 +555,10 @@ struct BandCursor {
 // Loading waves (whole chunks): one pipeline over all the workgroup's units.
 // Each step commits the next step's lines (maybe the next unit's first) into
 // the staging buffer the compute waves are not reading, issues the loads D
-// steps ahead, takes its LS shares of the horizontal pass, and meets the
-// compute waves at the step's barrier; a unit adds a barrier at its end (its
-// LDS free) and one at the next unit's start (its coefficients in place).
+// steps ahead, takes its LS shares of the horizontal pass (none where the
+// compute waves take them all), and meets the compute waves at the step's
+// barrier; a unit adds a barrier at its end (its LDS free) and one at the
+// next unit's start (its coefficients in place).
 // The staging buffer of a step is the parity of its index in the
 // workgroup's sequence of steps. These waves issue no stores to memory and
 // every iteration commits and re-issues one register set, so the loads in
