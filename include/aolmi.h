@@ -330,12 +330,15 @@ aol_status aol_graph_destroy(aol_graph* graph);
 
 /* Times schedule candidates on the buffers last set: first one segment
  * length for every stream x the column-band LDS budget (16..128 repetitions x
- * 150 or 76 KiB), then, classes with the most input first, each stream
+ * 150 or 76 KiB); then, where the int8-tap and split-tap streams share one
+ * launch, the weight of the int8-tap part in the division of the workgroups
+ * (500..1500 per mille); then, classes with the most input first, each stream
  * class's own segment length (16..128; a class: the two ratios and the width
- * class up to 640, 1280, 1920 pixels or wider) with the others held. Keeps the
- * fastest and appends it to the tuning cache (keyed by the device
- * architecture, the precision and the streams' sizes and filters).
- * Synchronises the stream (not a run call); results are unchanged. */
+ * class up to 640, 1280, 1920 pixels or wider) with the others held; last the
+ * weight again within 100 per mille of the best. Keeps the fastest and appends
+ * it to the tuning cache (keyed by the device architecture, the precision and
+ * the streams' sizes and filters). Synchronises the stream (not a run call);
+ * results are unchanged. */
 aol_status aol_autotune(aol_batch_plan* plan, hipStream_t stream);
 
 /* Rebuilds the plan with one schedule: segments of seg_reps repetitions (a
@@ -347,6 +350,16 @@ aol_status aol_autotune(aol_batch_plan* plan, hipStream_t stream);
  * previous schedule stays in place. Results are identical for every
  * schedule. */
 aol_status aol_batch_set_schedule(aol_batch_plan* plan, int32_t seg_reps, int32_t lds_budget);
+
+/* Rebuilds the plan with the current schedule and a new weight (per mille,
+ * 250 .. 4000; 1000 after aol_batch_set_schedule) of the int8-tap streams'
+ * estimated cost when they and the split-tap streams share one launch: a
+ * larger weight gives the int8-tap part more of the device's workgroups. No
+ * effect on a plan with one part. A configuration call like
+ * aol_batch_set_schedule (graphs must be captured again; AOL_ERR_INVALID for
+ * a weight out of range, the previous schedule stays in place). Results are
+ * identical for every weight. */
+aol_status aol_batch_set_part_weight(aol_batch_plan* plan, int32_t permille);
 
 /* The plan's current schedule as a JSON object (plan-owned string). */
 const char* aol_batch_schedule(aol_batch_plan* plan);

@@ -132,6 +132,7 @@ _proto("aol_graph_destroy", ctypes.c_int, ctypes.c_void_p)
 _proto("aol_autotune", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
 _proto("aol_batch_schedule", ctypes.c_char_p, ctypes.c_void_p)
 _proto("aol_batch_set_schedule", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32)
+_proto("aol_batch_set_part_weight", ctypes.c_int, ctypes.c_void_p, ctypes.c_int32)
 
 
 class aol_tiler(ctypes.Structure):
@@ -628,6 +629,10 @@ def aol_batch_set_schedule(plan, seg_reps: int, lds_budget: int):
     _check(_lib.aol_batch_set_schedule(plan, int(seg_reps), int(lds_budget)))
 
 
+def aol_batch_set_part_weight(plan, permille: int):
+    _check(_lib.aol_batch_set_part_weight(plan, int(permille)))
+
+
 class BatchPlan:
     """Many streams, one frame each per step, one persistent launch (optionally a graph)."""
 
@@ -687,6 +692,9 @@ class BatchPlan:
 
     def set_schedule(self, seg_reps: int, lds_budget: int):
         aol_batch_set_schedule(self._h, seg_reps, lds_budget)
+
+    def set_part_weight(self, permille: int):
+        aol_batch_set_part_weight(self._h, permille)
 
     def close(self):
         for g in self._graphs:

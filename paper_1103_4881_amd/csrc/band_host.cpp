@@ -177,12 +177,13 @@ BandUnit band_make_unit(const BandStream& S, const FilterBands& fb, int stream, 
   return U;
 }
 
-int64_t band_unit_cost(const BandStream& S, const BandUnit& U) {
-  // cycles of one workgroup, roughly: per step a fixed part, a part per
-  // staged chunk of the line and one per output block of the two passes;
-  // per unit its set-up and last vertical blocks
-  const int64_t vblocks_per_step = (int64_t)U.nbh * U.NBV / std::max(1, U.M);
-  return (int64_t)U.M * (600 + 8 * (int64_t)S.nch + 25 * (U.nbh + vblocks_per_step)) + 5000;
+int64_t band_unit_cost(const BandUnit& U) {
+  // cycles of one workgroup, roughly: per unit its set-up and last vertical
+  // blocks, per step the barrier-bound loop, per output block of the unit
+  // (columns x vertical blocks) its share of the two passes; a least-squares
+  // fit of per-unit durations timed inside the batch launch (both tap forms,
+  // units of 2 to 33 steps, bands of 15 to 60 blocks: about 9 % spread)
+  return 7000 + 1700 * (int64_t)U.M + 64 * (int64_t)U.nbh * U.NBV;
 }
 
 void band_frame_units(const BandStream* S, const FilterBands* const* fb, const int* seg, int n,
@@ -197,7 +198,7 @@ void band_frame_units(const BandStream* S, const FilterBands* const* fb, const i
     for (int sy = 0; sy < ns; ++sy)
       for (int xb = 0; xb < nxb; ++xb) {
         units.push_back(band_make_unit(S[i], *fb[i], i, xb, sy, sg));
-        cost.push_back(band_unit_cost(S[i], units.back()));
+        cost.push_back(band_unit_cost(units.back()));
       }
   }
 }

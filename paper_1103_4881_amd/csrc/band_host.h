@@ -44,7 +44,7 @@ int band_share_staging(BandStream* const* streams, const FilterBands* const* fbs
 BandUnit band_make_unit(const BandStream& S, const FilterBands& fb, int stream, int xb, int sy, int seg);
 
 // Estimated cost of a unit (arbitrary units: about cycles of a workgroup).
-int64_t band_unit_cost(const BandStream& S, const BandUnit& U);
+int64_t band_unit_cost(const BandUnit& U);
 
 // Longest segment (repetitions, a multiple of 16) of a stream: one lane per
 // vertical output block of a unit.

@@ -26,7 +26,12 @@ struct Schedule {
   int seg = 0;         // repetitions per segment (0: about 512 input lines)
   int budget = 150 * 1024;  // LDS budget per workgroup (picks the column band)
   std::vector<int> class_seg;  // per stream class: its own segment length (0 or absent: seg)
+  // Per mille: weight of the int8-tap part's estimated cost when one launch
+  // divides the device's workgroups between the two parts (the estimate
+  // misjudges the two bodies' relative speed by some tens of percent).
+  int part_weight = 1000;
 };
+constexpr int kPartWeightMin = 250, kPartWeightMax = 4000;
 
 // Stream classes of the tuner: ratio of each axis and width class (up to
 // 640, 1280, 1920 pixels, wider).
@@ -229,6 +234,7 @@ static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
     double ca = 0, cb = 0;
     for (int64_t c : A.cost) ca += (double)c;
     for (int64_t c : B.cost) cb += (double)c;
+    ca *= sc.part_weight / 1000.0;
     int ga = (int)(total * ca / std::max(ca + cb, 1.0) + 0.5);
     ga = std::max(1, std::min(total - 1, ga));
     aol_status st = batch_place_part(A, ga);
@@ -253,10 +259,11 @@ static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
   bp->streams = std::move(streams);
   bp->sched = sc;
-  char buf[200];
+  char buf[240];
   snprintf(buf, sizeof buf,
            "{\"seg\": %d, \"lds_budget\": %d, \"units\": %d, \"grid\": %d, \"lds\": %d, \"launches\": %d, "
-           "\"class_segs\": [", sc.seg, sc.budget, units, grid, lds, launches);
+           "\"part_weight\": %d, \"class_segs\": [",
+           sc.seg, sc.budget, units, grid, lds, launches, sc.part_weight);
   bp->sched_json = buf;
   for (size_t c = 0; c < sc.class_seg.size(); ++c) bp->sched_json += (c ? ", " : "") + std::to_string(sc.class_seg[c]);
   bp->sched_json += "]}";
@@ -344,8 +351,8 @@ static std::string batch_key(const aol_batch_plan* bp) {
   return k + buf;
 }
 
-// Tiny line-oriented cache: "key seg budget n_classes class_seg..." per line
-// (the last line of a key wins).
+// Tiny line-oriented cache: "key seg budget n_classes class_seg... part_weight"
+// per line (the last line of a key wins; a line without the weight: 1000).
 static bool cache_lookup(const std::string& path, const std::string& key, Schedule* sc) {
   FILE* f = fopen(path.c_str(), "r");
   if (!f) return false;
@@ -358,16 +365,21 @@ static bool cache_lookup(const std::string& path, const std::string& key, Schedu
       sc->seg = seg;
       sc->budget = budget;
       sc->class_seg.clear();
+      sc->part_weight = 1000;
       int n = 0, m = 0;
       const char* rest = line + used;
-      if (sscanf(rest, "%d%n", &n, &m) == 1 && n > 0 && n <= 4096) {
+      if (sscanf(rest, "%d%n", &n, &m) == 1 && n >= 0 && n <= 4096) {
         rest += m;
-        for (int c = 0; c < n; ++c) {
+        int c = 0;
+        for (; c < n; ++c) {
           int v = 0;
           if (sscanf(rest, "%d%n", &v, &m) != 1) break;
           rest += m;
           sc->class_seg.push_back(v);
         }
+        int wgt = 0;
+        if (c == n && sscanf(rest, "%d", &wgt) == 1 && wgt >= kPartWeightMin && wgt <= kPartWeightMax)
+          sc->part_weight = wgt;
       }
       found = true;
     }
@@ -381,7 +393,7 @@ static void cache_store(const std::string& path, const std::string& key, const S
   if (!f) return;
   fprintf(f, "%s %d %d %d", key.c_str(), sc.seg, sc.budget, (int)sc.class_seg.size());
   for (int v : sc.class_seg) fprintf(f, " %d", v);
-  fprintf(f, "\n");
+  fprintf(f, " %d\n", sc.part_weight);
   fclose(f);
 }
 
@@ -639,26 +651,43 @@ aol_status aol_autotune(aol_batch_plan* plan, hipStream_t stream) {
   Schedule best = plan->sched;
   float best_ms = 1e30f;
   aol_status st = AOL_OK;
+  auto trial = [&](const Schedule& sc) {
+    float ms = 0.f;
+    st = time_schedule(plan, sc, stream, e0, e1, &ms);
+    if (!st && ms >= 0.f && ms < best_ms) {
+      best_ms = ms;
+      best = sc;
+    }
+    return st == AOL_OK;
+  };
+  // the weight of the int8-tap part when both parts share one launch
+  auto weights = [&](std::initializer_list<int> deltas) {
+    if (best_ms >= 1e30f || batch_build(plan, best) != AOL_OK || !plan->dual) return true;
+    const Schedule base = best;
+    for (int d : deltas) {
+      Schedule sc = base;
+      sc.part_weight = base.part_weight + d;
+      if (sc.part_weight < kPartWeightMin || sc.part_weight > kPartWeightMax) continue;
+      if (!trial(sc)) return false;
+    }
+    return true;
+  };
   // 1. one segment length and LDS budget (column band) for every stream
   const int segs[] = {16, 32, 64, 128};
   const int budgets[] = {150 * 1024, 76 * 1024};
-  for (int budget : budgets) {
+  bool go = true;
+  for (int budget : budgets)
     for (int seg : segs) {
       Schedule sc;
       sc.seg = seg;
       sc.budget = budget;
-      float ms = 0.f;
-      if ((st = time_schedule(plan, sc, stream, e0, e1, &ms))) break;
-      if (ms >= 0.f && ms < best_ms) {
-        best_ms = ms;
-        best = sc;
-      }
+      if (go) go = trial(sc);
     }
-    if (st) break;
-  }
-  // 2. then each stream class's own segment length, classes with the most
-  // input first, the others held at their best so far (one pass)
-  if (!st && best_ms < 1e30f) {
+  // 2. the parts' weight, coarse
+  if (go) go = weights({-500, -400, -300, -200, -100, 100, 250, 500});
+  // 3. each stream class's own segment length, classes with the most input
+  // first, the others held at their best so far (one pass)
+  if (go && best_ms < 1e30f) {
     std::vector<int> order(plan->cls_bytes.size());
     for (size_t c = 0; c < order.size(); ++c) order[c] = (int)c;
     std::stable_sort(order.begin(), order.end(),
@@ -666,19 +695,16 @@ aol_status aol_autotune(aol_batch_plan* plan, hipStream_t stream) {
     best.class_seg.assign(order.size(), 0);
     const int class_segs[] = {16, 32, 48, 64, 96, 128};
     for (int c : order) {
+      const Schedule base = best;
       for (int seg : class_segs) {
-        Schedule sc = best;
+        Schedule sc = base;
         sc.class_seg[c] = seg;
-        float ms = 0.f;
-        if ((st = time_schedule(plan, sc, stream, e0, e1, &ms))) break;
-        if (ms >= 0.f && ms < best_ms) {
-          best_ms = ms;
-          best = sc;
-        }
+        if (go) go = trial(sc);
       }
-      if (st) break;
     }
   }
+  // 4. the parts' weight again, fine, around the best
+  if (go) go = weights({-100, -50, 50, 100});
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st) return st;
@@ -699,6 +725,22 @@ aol_status aol_batch_set_schedule(aol_batch_plan* plan, int32_t seg_reps, int32_
   if (st) {
     const std::string msg = last_error();
     const Schedule old = plan->sched;
+    if (batch_build(plan, old) != AOL_OK) return fail(AOL_ERR_HIP, "restoring the previous schedule failed");
+    return fail(st, "%s", msg.c_str());
+  }
+  return ok();
+}
+
+aol_status aol_batch_set_part_weight(aol_batch_plan* plan, int32_t permille) {
+  if (!plan) return fail(AOL_ERR_INVALID, "NULL plan");
+  if (permille < kPartWeightMin || permille > kPartWeightMax)
+    return fail(AOL_ERR_INVALID, "part weight must be within %d .. %d per mille", kPartWeightMin, kPartWeightMax);
+  const Schedule old = plan->sched;
+  Schedule sc = old;
+  sc.part_weight = permille;
+  aol_status st = batch_build(plan, sc);
+  if (st) {
+    const std::string msg = last_error();
     if (batch_build(plan, old) != AOL_OK) return fail(AOL_ERR_HIP, "restoring the previous schedule failed");
     return fail(st, "%s", msg.c_str());
   }

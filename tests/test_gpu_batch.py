@@ -2,6 +2,8 @@
 optionally a captured graph) against the CPU oracle: integer bit-exact,
 float within 1e-3 normalised pixels of the float64 oracle."""
 
+import json
+
 import numpy as np
 import pytest
 
@@ -302,6 +304,35 @@ def test_batch_every_tuner_candidate_identical():
                 for i in range(len(mix)):
                     assert torch.equal(outs[i], first[i]), f"seg {seg} budget {budget}: stream {i} differs"
     assert n_cand >= 4
+    plan.close()
+
+
+def test_batch_part_weights_give_identical_outputs():
+    """The 64-stream mix (int8-tap and split-tap streams in one launch) with the workgroups divided
+    between the two parts at skewed weights: every stream's output equals the oracle at each
+    weight, and a weight out of range is refused with the last one kept."""
+    mix, filt, streams = _mix64()
+    plan = aol.BatchPlan(streams, "u8")
+    g = synthgen.rng_for(2011, 13)
+    frames = [synthgen.gradient_plane(g, s.h, s.w) for s in mix]
+    ins = [torch.from_numpy(f).cuda() for f in frames]
+    want = [pp.downscale_u8(frames[i], filt[(s.p, s.q, s.taps)][1], filt[(s.p, s.q, s.taps)][1])
+            for i, s in enumerate(mix)]
+    for k, wgt in enumerate((300, 1000, 2500)):
+        plan.set_part_weight(wgt)
+        sched = json.loads(plan.schedule())
+        assert sched["part_weight"] == wgt and sched["launches"] == 1, sched
+        outs = [torch.full(plan.out_shapes[i], 0xFF if k % 2 else 0x00, dtype=torch.uint8, device="cuda")
+                for i in range(len(mix))]
+        plan.set_pointers(ins, outs)
+        plan.run()
+        torch.cuda.synchronize()
+        for i in range(len(mix)):
+            np.testing.assert_array_equal(outs[i].cpu().numpy(), want[i], err_msg=f"weight {wgt}: stream {i}")
+    with pytest.raises(aol.AolError) as ei:
+        plan.set_part_weight(100)
+    assert ei.value.status == aol.AOL_ERR_INVALID
+    assert json.loads(plan.schedule())["part_weight"] == 2500
     plan.close()
 
 
