@@ -410,7 +410,7 @@ BATCH_FRAMES = 30
 
 def bench_batch(fmt="u8", steps=BATCH_FRAMES, warmup=BATCH_FRAMES, only_size=None):
     """64 streams of uneven sizes/ratios/taps, 30 frames each; one step = one frame of every
-    stream = one pointer-table update + one launch of the persistent kernel.
+    stream = one launch of the persistent kernel over that frame slot's buffer set.
     only_size=(h, w): the subset of the mix's streams of that size."""
     import torch
     import paper_1103_4881_amd as aol
@@ -442,17 +442,16 @@ def bench_batch(fmt="u8", steps=BATCH_FRAMES, warmup=BATCH_FRAMES, only_size=Non
         plan.set_pointers([ins[i][0] for i in range(len(mix))], [outs[i][0] for i in range(len(mix))], s)
         plan.autotune(s)
 
-        # the frame slots' pointer arrays, built once (a serving loop over a ring of frame
-        # buffers keeps them the same way); a step points the plan at its slot (a small
-        # enqueued kernel) and launches the persistent kernel (measured faster than one
-        # graph launch per slot)
-        arrays = [plan.pointer_arrays([ins[i][k] for i in range(len(mix))], [outs[i][k] for i in range(len(mix))])
-                  for k in range(BATCH_FRAMES)]
+        # one buffer set (pointer table) per frame slot, made once, as a serving loop over a
+        # ring of frame buffers keeps them: a step is one launch of the persistent kernel
+        # (measured faster than a pointer update + launch, or one graph launch per slot)
+        sets = [plan.buffers(plan.pointer_arrays([ins[i][k] for i in range(len(mix))],
+                                                 [outs[i][k] for i in range(len(mix))]))
+                for k in range(BATCH_FRAMES)]
         count = [0]
 
         def step():
-            plan.set_pointer_arrays(arrays[count[0] % BATCH_FRAMES], s)
-            plan.run(s)
+            plan.run_buffers(sets[count[0] % BATCH_FRAMES], s)
             count[0] += 1
 
         ms_step, ms_kernel, ms_med = time_launches(step, steps, warmup, s)

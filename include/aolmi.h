@@ -16,8 +16,8 @@
  *    the device tables they allocate at creation (filter fragments, tile
  *    lists, pointer tables) and free them on destroy.
  *  - Run calls (aol_downscale_u8, aol_downscale_f, aol_downscale_u8_unfused,
- *    aol_downscale_u8_unfused_static, aol_batch_run, aol_graph_launch,
- *    aol_wsum_run, aol_linear_run) only enqueue work on the given stream:
+ *    aol_downscale_u8_unfused_static, aol_batch_run, aol_batch_run_buffers,
+ *    aol_graph_launch, aol_wsum_run, aol_linear_run) only enqueue work on the given stream:
  *    they never allocate and never synchronise. They check pointers and
  *    alignment and report launch errors; faults inside a kernel surface at
  *    the caller's next synchronisation.
@@ -295,6 +295,7 @@ typedef struct aol_stream_desc {
 
 typedef struct aol_batch_plan aol_batch_plan;
 typedef struct aol_graph aol_graph;
+typedef struct aol_buffer_set aol_buffer_set;
 
 /* tune_cache: path of a text file of tuned schedules (read here, appended
  * by aol_autotune), or NULL. All streams use precision prec. */
@@ -327,6 +328,23 @@ aol_status aol_batch_graph_create_pointers(aol_batch_plan* plan, const void* con
                                            hipStream_t stream, aol_graph** out);
 aol_status aol_graph_launch(aol_graph* graph, hipStream_t stream);
 aol_status aol_graph_destroy(aol_graph* graph);
+
+/* A buffer set: one frame's buffers of every stream (d_in, d_out: n device
+ * pointers each, 16-byte aligned, checked here) in a pointer table of its own,
+ * uploaded now (a configuration call: allocates and synchronises). A serving
+ * loop over a ring of frame buffers makes one set per slot and runs each step
+ * with aol_batch_run_buffers: one launch, no pointer update. A set belongs to
+ * the plan it was made for and stays valid across that plan's schedule
+ * changes (aol_autotune, aol_batch_set_schedule); it holds no reference to the
+ * buffers, which the caller keeps alive. Destroy sets before or after their
+ * plan, in any order. */
+aol_status aol_batch_buffers_create(aol_batch_plan* plan, const void* const* d_in, void* const* d_out,
+                                    aol_buffer_set** out);
+/* Run call: the plan's launch over the set's buffers (the plan's own pointer
+ * table is neither read nor changed). AOL_ERR_INVALID for a set made for
+ * another plan. */
+aol_status aol_batch_run_buffers(aol_batch_plan* plan, const aol_buffer_set* set, hipStream_t stream);
+aol_status aol_batch_buffers_destroy(aol_buffer_set* set);
 
 /* Times schedule candidates on the buffers last set: first one segment
  * length for every stream x the column-band LDS budget (16..128 repetitions x

@@ -128,6 +128,10 @@ _proto("aol_batch_graph_create", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
 _proto("aol_batch_graph_create_pointers", ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
        ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p))
 _proto("aol_graph_launch", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
+_proto("aol_batch_buffers_create", ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p))
+_proto("aol_batch_run_buffers", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_proto("aol_batch_buffers_destroy", ctypes.c_int, ctypes.c_void_p)
 _proto("aol_graph_destroy", ctypes.c_int, ctypes.c_void_p)
 _proto("aol_autotune", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
 _proto("aol_batch_schedule", ctypes.c_char_p, ctypes.c_void_p)
@@ -613,6 +617,20 @@ def aol_graph_launch(graph, stream=None):
     _check(_lib.aol_graph_launch(graph, _stream_handle(stream)))
 
 
+def aol_batch_buffers_create(plan, d_in, d_out):
+    b = ctypes.c_void_p()
+    _check(_lib.aol_batch_buffers_create(plan, d_in, d_out, ctypes.byref(b)))
+    return b
+
+
+def aol_batch_run_buffers(plan, buffers, stream=None):
+    _check(_lib.aol_batch_run_buffers(plan, buffers, _stream_handle(stream)))
+
+
+def aol_batch_buffers_destroy(buffers):
+    _check(_lib.aol_batch_buffers_destroy(buffers))
+
+
 def aol_graph_destroy(graph):
     _check(_lib.aol_graph_destroy(graph))
 
@@ -643,6 +661,7 @@ class BatchPlan:
         self.out_shapes = [aol_downscale_output_shape(h, w, hf, vf) for (h, w), (hf, vf) in zip(self.shapes, self.filters)]
         self._h = aol_batch_plan_create(streams, precision, tune_cache)
         self._graphs = []
+        self._buffer_sets = []
 
     def set_pointers(self, ins, outs, stream=None):
         self.set_pointer_arrays(self.pointer_arrays(ins, outs), stream)
@@ -684,6 +703,17 @@ class BatchPlan:
         self._graphs.append(g)
         return g
 
+    def buffers(self, arrays):
+        """A buffer set: the buffers of `pointer_arrays` in a pointer table of its own (one
+        per frame slot of a serving loop; the tensors must stay alive)."""
+        b = aol_batch_buffers_create(self._h, arrays[0], arrays[1])
+        self._buffer_sets.append(b)
+        return b
+
+    def run_buffers(self, buffers, stream=None):
+        """One step over a buffer set: one launch, the plan's own pointer table untouched."""
+        aol_batch_run_buffers(self._h, buffers, stream)
+
     def autotune(self, stream=None):
         aol_autotune(self._h, stream)
 
@@ -700,6 +730,9 @@ class BatchPlan:
         for g in self._graphs:
             aol_graph_destroy(g)
         self._graphs = []
+        for b in getattr(self, "_buffer_sets", []):
+            aol_batch_buffers_destroy(b)
+        self._buffer_sets = []
         if getattr(self, "_h", None):
             aol_batch_plan_destroy(self._h)
             self._h = None

@@ -102,6 +102,11 @@ struct aol_graph {
   uint64_t captured = 0;
 };
 
+struct aol_buffer_set {
+  std::shared_ptr<uint64_t> owner;  // the generation counter of the plan it was made for
+  DeviceBuf d_ptrs;                 // pointer table (in, out per stream), filled at creation
+};
+
 // One part's streams, units and balanced order for a schedule.
 static aol_status batch_build_part(aol_batch_plan* bp, aol_batch_plan::Part& P, const Schedule& sc,
                                    std::vector<BandStream>& streams) {
@@ -540,6 +545,35 @@ aol_status aol_batch_run(aol_batch_plan* plan, hipStream_t stream) {
   if (!plan->pointers_set) return fail(AOL_ERR_INVALID, "aol_batch_set_pointers was never called");
   aol_status st = batch_launch(plan, stream);
   return st ? st : ok();
+}
+
+aol_status aol_batch_buffers_create(aol_batch_plan* plan, const void* const* d_in, void* const* d_out,
+                                    aol_buffer_set** out) {
+  if (!plan || !out) return fail(AOL_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  std::vector<const void*> ptrs;
+  if (aol_status st = batch_pointer_list(plan, d_in, d_out, ptrs)) return st;
+  aol_buffer_set* b = new (std::nothrow) aol_buffer_set();
+  if (!b) return fail(AOL_ERR_NOMEM, "buffer set allocation");
+  b->owner = plan->generation;
+  if (aol_status st = b->d_ptrs.upload(ptrs.data(), ptrs.size() * sizeof(void*))) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return ok();
+}
+
+aol_status aol_batch_run_buffers(aol_batch_plan* plan, const aol_buffer_set* set, hipStream_t stream) {
+  if (!plan || !set) return fail(AOL_ERR_INVALID, "NULL argument");
+  if (set->owner != plan->generation) return fail(AOL_ERR_INVALID, "the buffer set was made for another plan");
+  aol_status st = batch_launch(plan, stream, set->d_ptrs.ptr);
+  return st ? st : ok();
+}
+
+aol_status aol_batch_buffers_destroy(aol_buffer_set* set) {
+  delete set;
+  return ok();
 }
 
 }  // extern "C"

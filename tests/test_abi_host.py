@@ -136,4 +136,6 @@ def test_one_shot_weighted_sum_validation_on_host():
 def test_schedule_calls_reject_null_plans():
     _expect(aol.AOL_ERR_INVALID, aol.aol_batch_set_schedule, None, 0, 150 * 1024)
     _expect(aol.AOL_ERR_INVALID, aol.aol_batch_set_part_weight, None, 1000)
+    _expect(aol.AOL_ERR_INVALID, aol.aol_batch_run_buffers, None, None, 0)
+    _expect(aol.AOL_ERR_INVALID, aol.aol_batch_buffers_create, None, None, None)
     assert aol.aol_plan_schedule(None, 1) == ""

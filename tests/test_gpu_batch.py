@@ -107,6 +107,44 @@ def test_batch_graphs_with_pointers_per_frame_slot(fill):
 
 
 @pytest.mark.parametrize("fill", FILLS)
+def test_batch_buffer_sets_per_frame_slot(fill):
+    """One buffer set per frame slot, run in turn and out of order, across a schedule change,
+    with the plan's own table pointed elsewhere: every output against the oracle; a set is
+    refused by another plan."""
+    st = _streams(MIX, seed=6)
+    plan = aol.BatchPlan([(h, w, hf, vf) for (h, w, hf, vf, _, _) in st], "u8")
+    slots = 3
+    frames = _frames(MIX, slots + 1, 17)
+    ins = [[torch.from_numpy(fr).cuda() for fr in fs] for fs in frames]
+    outs = [[torch.full(plan.out_shapes[i], fill, dtype=torch.uint8, device="cuda") for _ in range(slots + 1)]
+            for i in range(len(st))]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        sets = [plan.buffers(plan.pointer_arrays([ins[i][k] for i in range(len(st))],
+                                                 [outs[i][k] for i in range(len(st))])) for k in range(slots)]
+        # the plan's own table: the spare slot, which no buffer-set run may touch
+        plan.set_pointers([ins[i][slots] for i in range(len(st))], [outs[i][slots] for i in range(len(st))], s)
+        for rep, k in enumerate([0, 1, 2, 1, 0, 2]):
+            if rep == 3:
+                plan.set_schedule(32, 150 * 1024)
+            for i in range(len(st)):
+                outs[i][k].fill_(fill)
+            plan.run_buffers(sets[k], s)
+            s.synchronize()
+            for i, (h, w, hf, vf, of, ov) in enumerate(st):
+                np.testing.assert_array_equal(outs[i][k].cpu().numpy(), pp.downscale_u8(frames[i][k], of, ov),
+                                              err_msg=f"run {rep} slot {k} stream {i}")
+        for i in range(len(st)):
+            assert bool((outs[i][slots] == fill).all()), f"stream {i}: the plan's own buffers were written"
+        other = aol.BatchPlan([(h, w, hf, vf) for (h, w, hf, vf, _, _) in st], "u8")
+        with pytest.raises(aol.AolError) as ei:
+            other.run_buffers(sets[0], s)
+        assert ei.value.status == aol.AOL_ERR_INVALID
+        other.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("fill", FILLS)
 def test_batch_autotune_keeps_results(tmp_path, fill):
     st = _streams(MIX[:4], seed=3)
     cache = str(tmp_path / "tune.txt")
