@@ -120,7 +120,7 @@ struct BandStream {
   // the next unit's first lines can be staged while a unit finishes.
   int32_t lds_x, lds_z, lds_fh, lds_fv, lds_bh, lds_bv;
   int32_t vec_in;          // line length a multiple of one chunk and pitch chunk aligned
-  int32_t vec_out;         // output pitch a multiple of 4 elements
+  int32_t vec_out;         // 4 or 2: the larger of them dividing the output pitch (elements), else 0
   int32_t xbuf;            // bytes from staging buffer 0 to buffer 1 (the same for every stream of a launch)
   int32_t lds_vt;          // LDS byte offset of the vertical block table (64 entries, then 64 window ends)
   const AxisBand* hb;      // one period (16 repetitions) of each axis

@@ -47,6 +47,7 @@ namespace aol {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
@@ -466,7 +467,7 @@ __device__ __forceinline__ void band_unit(const BandLaunch& L, int u, BandStream
   G.col_end = U.col_end;
   G.nbh = U.nbh;
   G.vec_in = S.vec_in && L.aligned;
-  G.vec_out = S.vec_out && L.aligned;
+  G.vec_out = L.aligned ? S.vec_out : 0;
 }
 
 // The workgroup's slot in the rounds. Workgroups are dispatched to the 8
@@ -789,7 +790,11 @@ __device__ __forceinline__ void band_body(const BandLaunch& L, uint8_t* lds) {
         }
         const int bias = ELEM == kU8 ? *reinterpret_cast<const int*>(bv + lb * 64 + n * 4) : 0;
         const int orow = G.orow0 + 16 * B + n;
-        const bool rows_in = G.vec_out && G.orow0 + 16 * B + 16 <= G.row_end;  // uniform
+        // uniform: the block's 16 rows inside the plane, with rows 4- (rows_in)
+        // or 2-element aligned (rows_in2)
+        const bool rows_all = G.orow0 + 16 * B + 16 <= G.row_end;
+        const bool rows_in = G.vec_out == 4 && rows_all;
+        const bool rows_in2 = G.vec_out != 0 && rows_all;
         gdst_t rowp = G.dst + ((int64_t)orow * S.out_pitch + G.ocol0 + 4 * g) * (ELEM == kU8 ? 1 : 4);
         if constexpr (ELEM == kU8 && NB == 4) {
           // Integer outputs by pairs of adjacent column blocks: one swap of
@@ -826,8 +831,16 @@ __device__ __forceinline__ void band_body(const BandLaunch& L, uint8_t* lds) {
               if (q > 0 && cbA >= G.nbh) break;
               const auto sw = __builtin_amdgcn_permlane16_swap(y4[2 * q], y4[2 * q + 1], false, false);
               // uniform: both blocks whole and inside the plane
-              if (rows_in && pitch8 && cbA + 1 < G.nbh && G.ocol0 + 16 * cbA + 32 <= G.col_end) {
+              const bool pair_in = cbA + 1 < G.nbh && G.ocol0 + 16 * cbA + 32 <= G.col_end;
+              if (rows_in && pitch8 && pair_in) {
                 *(AOL_GLOBAL v2u*)(rowq + 16 * cbA) = v2u{(uint32_t)sw[0], (uint32_t)sw[1]};
+              } else if (rows_in && pair_in) {
+                *(AOL_GLOBAL uint32_t*)(rowq + 16 * cbA) = (uint32_t)sw[0];
+                *(AOL_GLOBAL uint32_t*)(rowq + 16 * cbA + 4) = (uint32_t)sw[1];
+              } else if (rows_in2 && pair_in) {
+#pragma unroll
+                for (int h = 0; h < 4; ++h)
+                  *(AOL_GLOBAL uint16_t*)(rowq + 16 * cbA + 2 * h) = (uint16_t)((uint32_t)sw[h >> 1] >> (16 * (h & 1)));
               } else if (orow < G.row_end) {
 #pragma unroll
                 for (int jj = 0; jj < 2; ++jj) {
@@ -886,7 +899,8 @@ __device__ __forceinline__ void band_body(const BandLaunch& L, uint8_t* lds) {
               const int cb = cb0 + j * NW;
               if (j > 0 && cb >= G.nbh) break;
               // uniform: the whole 16x16 output block inside the plane
-              const bool inside = rows_in && G.ocol0 + 16 * cb + 16 <= G.col_end;
+              const bool cols_in = G.ocol0 + 16 * cb + 16 <= G.col_end;
+              const bool inside = rows_in && cols_in, inside2 = rows_in2 && cols_in;
               const int col = G.ocol0 + 16 * cb + 4 * g;
               if constexpr (ELEM == kU8) {
                 v4i r = acc[j];
@@ -894,6 +908,9 @@ __device__ __forceinline__ void band_body(const BandLaunch& L, uint8_t* lds) {
                 const uint32_t y4 = b_quant4(r, 0);
                 if (inside) {
                   *(AOL_GLOBAL uint32_t*)(rowp + 16 * cb) = y4;
+                } else if (inside2) {
+                  *(AOL_GLOBAL uint16_t*)(rowp + 16 * cb) = (uint16_t)y4;
+                  *(AOL_GLOBAL uint16_t*)(rowp + 16 * cb + 2) = (uint16_t)(y4 >> 16);
                 } else if (orow < G.row_end) {
                   gdst_t op = rowp + 16 * cb;
   #pragma unroll
@@ -903,6 +920,9 @@ __device__ __forceinline__ void band_body(const BandLaunch& L, uint8_t* lds) {
               } else {
                 if (inside) {
                   *(AOL_GLOBAL v4f*)(rowp + 64 * cb) = accf[j];
+                } else if (inside2) {
+                  *(AOL_GLOBAL v2f*)(rowp + 64 * cb) = v2f{accf[j][0], accf[j][1]};
+                  *(AOL_GLOBAL v2f*)(rowp + 64 * cb + 8) = v2f{accf[j][2], accf[j][3]};
                 } else if (orow < G.row_end) {
                   AOL_GLOBAL float* op = (AOL_GLOBAL float*)(rowp + 64 * cb);
   #pragma unroll

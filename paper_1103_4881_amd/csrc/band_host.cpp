@@ -141,7 +141,7 @@ aol_status build_band_stream(const FilterBands& fb, int64_t h, int64_t w, int64_
   // at most 64 vertical output blocks per unit (one per lane of a table)
   S.seg = std::min(S.seg, 16 * std::max(1, 64 / vb.p));
   S.vec_in = (w % E == 0) && (in_pitch % E == 0);
-  S.vec_out = (out_pitch % 4 == 0) && ((hb.p * xr) % 4 == 0);
+  S.vec_out = (hb.p * xr) % 4 != 0 ? 0 : out_pitch % 4 == 0 ? 4 : out_pitch % 2 == 0 ? 2 : 0;
   S.hb = (const AxisBand*)fb.d_hb.ptr;
   S.vb = (const AxisBand*)fb.d_vb.ptr;
   S.hfrag = fb.d_hfrag.ptr;

@@ -171,6 +171,20 @@ def test_output_pitches_paired_stores(w, out_pad):
     np.testing.assert_array_equal(Y, pp.downscale_u8(X, of, ov))
 
 
+@pytest.mark.parametrize("w,out_pad", [(1280, 0), (1275, 0), (1280, 1), (1280, 2), (1278, 0)])
+def test_output_pitches_split_taps(w, out_pad):
+    """2/3 with split taps, three frames: output rows of 854 / 850 / 852 bytes with pitches
+    6, 2, 0 and 4 modulo 8 and odd ones (dword, half-word and byte stores)."""
+    hf, of = _filters(2, 3, 14)
+    X = np.stack([synthgen.uniform_frame(40 + f, 96, w, idx=3) for f in range(3)])
+    probe = aol.DownscalePlan([(96, w)], hf, hf, "u8")
+    sched = probe.schedule(3)
+    probe.close()
+    assert sched["kernel"] == "band" and sched["split"] == 1, sched
+    (Y,) = _run_u8([X], hf, hf, out_pitch_pad=out_pad)
+    np.testing.assert_array_equal(Y, pp.downscale_u8(X, of, of))
+
+
 def test_i420_frames_every_tile_shape_identical():
     """Three planes, several frames, every tile shape: identical bytes (independent elementary tasks)."""
     Yp, Up, Vp = synthgen.yuv420_frames(7, 3, 360, 640)
@@ -318,7 +332,7 @@ def test_float_path_within_tolerance(fmt):
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp16"])
-@pytest.mark.parametrize("case", [(33, 71, 2, 3, 16), (19, 5, 1, 2, 8), (130, 300, 3, 8, 11)])
+@pytest.mark.parametrize("case", [(33, 71, 2, 3, 16), (19, 5, 1, 2, 8), (130, 300, 3, 8, 11), (40, 75, 2, 3, 14)])
 def test_float_path_odd_shapes(fmt, case):
     h, w, p, q, T = case
     hf, of = _filters(p, q, T)
