@@ -341,8 +341,11 @@ aol_status aol_graph_destroy(aol_graph* graph);
 aol_status aol_batch_buffers_create(aol_batch_plan* plan, const void* const* d_in, void* const* d_out,
                                     aol_buffer_set** out);
 /* Run call: the plan's launch over the set's buffers (the plan's own pointer
- * table is neither read nor changed). AOL_ERR_INVALID for a set made for
- * another plan. */
+ * table is neither read nor changed). Launches over different sets share only
+ * read-only tables, so they may run concurrently on different streams (a
+ * serving loop alternating two streams overlaps one step's last workgroups
+ * with the next step's first). AOL_ERR_INVALID for a set made for another
+ * plan. */
 aol_status aol_batch_run_buffers(aol_batch_plan* plan, const aol_buffer_set* set, hipStream_t stream);
 aol_status aol_batch_buffers_destroy(aol_buffer_set* set);
 
@@ -363,8 +366,9 @@ aol_status aol_autotune(aol_batch_plan* plan, hipStream_t stream);
  * multiple of 16; 0: about 512 input lines, shortened for streams whose units
  * would exceed a workgroup's fair share) and column bands that fit
  * lds_budget bytes of LDS per workgroup (16 KiB .. 160 KiB). A configuration
- * call (synchronous uploads), not a run call; graphs captured before it must
- * be captured again. AOL_ERR_UNSUPPORTED when the schedule does not fit; the
+ * call, not a run call: it waits for all work on the device (launches in
+ * flight read the tables it rewrites), then uploads; graphs captured before it
+ * must be captured again. AOL_ERR_UNSUPPORTED when the schedule does not fit; the
  * previous schedule stays in place. Results are identical for every
  * schedule. */
 aol_status aol_batch_set_schedule(aol_batch_plan* plan, int32_t seg_reps, int32_t lds_budget);

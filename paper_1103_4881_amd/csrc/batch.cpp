@@ -212,6 +212,10 @@ static aol_status batch_place_part(aol_batch_plan::Part& P, int grid) {
 }
 
 static aol_status batch_build(aol_batch_plan* bp, const Schedule& sc) {
+  // Launches of this plan still in flight on any stream read the tables
+  // rewritten below (plain copies do not wait for non-blocking streams).
+  hipError_t es = hipDeviceSynchronize();
+  if (es != hipSuccess) return hip_fail(es, "hipDeviceSynchronize");
   ++*bp->generation;  // first: a build that fails halfway has already rewritten tables
   std::vector<BandStream> streams(bp->n);
   int units = 0, grid = 0, lds = 0, launches = 0;
