@@ -145,6 +145,46 @@ def test_batch_buffer_sets_per_frame_slot(fill):
 
 
 @pytest.mark.parametrize("fill", FILLS)
+def test_batch_buffer_sets_on_two_streams(fill):
+    """Buffer sets run on two streams in turn with no wait between them (the sets write
+    different frame slots), and a schedule change issued while those launches may still
+    run: every slot against the oracle, before and after the change."""
+    st = _streams(MIX, seed=8)
+    plan = aol.BatchPlan([(h, w, hf, vf) for (h, w, hf, vf, _, _) in st], "u8")
+    slots = 4
+    first = _frames(MIX, slots, 23)
+    second = _frames(MIX, slots, 41)
+    ins = [[torch.from_numpy(fr).cuda() for fr in fs] for fs in first]
+    outs = [[torch.full(plan.out_shapes[i], fill, dtype=torch.uint8, device="cuda") for _ in range(slots)]
+            for i in range(len(st))]
+    sets = [plan.buffers(plan.pointer_arrays([ins[i][k] for i in range(len(st))],
+                                             [outs[i][k] for i in range(len(st))])) for k in range(slots)]
+    pair = (torch.cuda.Stream(), torch.cuda.Stream())
+    torch.cuda.synchronize()
+    for k in range(slots):
+        plan.run_buffers(sets[k], pair[k & 1])
+    plan.set_schedule(32, 76 * 1024)  # waits for the launches above before rewriting tables
+    torch.cuda.synchronize()
+    for i, (h, w, hf, vf, of, ov) in enumerate(st):
+        for k in range(slots):
+            np.testing.assert_array_equal(outs[i][k].cpu().numpy(), pp.downscale_u8(first[i][k], of, ov),
+                                          err_msg=f"first pass slot {k} stream {i}")
+    for i in range(len(st)):
+        for k in range(slots):
+            ins[i][k].copy_(torch.from_numpy(second[i][k]))
+            outs[i][k].fill_(fill)
+    torch.cuda.synchronize()
+    for r in range(2 * slots):  # a slot returns to the same stream, so its two runs stay ordered
+        plan.run_buffers(sets[r % slots], pair[r & 1])
+    torch.cuda.synchronize()
+    for i, (h, w, hf, vf, of, ov) in enumerate(st):
+        for k in range(slots):
+            np.testing.assert_array_equal(outs[i][k].cpu().numpy(), pp.downscale_u8(second[i][k], of, ov),
+                                          err_msg=f"second pass slot {k} stream {i}")
+    plan.close()
+
+
+@pytest.mark.parametrize("fill", FILLS)
 def test_batch_autotune_keeps_results(tmp_path, fill):
     st = _streams(MIX[:4], seed=3)
     cache = str(tmp_path / "tune.txt")
