@@ -293,6 +293,26 @@ aol_status aol_linear_plan_create(const aol_tiler* in, const aol_tiler* out, con
   std::vector<int32_t> ioff, ifd, ooff, ofd;
   side(in, n_in, n_pad, a.S, a.st, a.o, a.P, a.lo, a.hi, a.inc, ioff, ifd);
   side(out, n_out, NOUT, a.So, a.sto, a.oo, a.Po, a.olo, a.ohi, a.oinc, ooff, ofd);
+  // Rotation of a row's points over its threads (a schedule choice; results
+  // do not depend on it): start the threads at the first point of a cyclic
+  // run of points whose input pattern leaves the array along an axis that
+  // moves with the row (axes fixed along a row wrap every point of it or none).
+  a.rot = 0;
+  if (a.R[a.rr - 1] <= kLinThreads) {
+    const int R = a.R[a.rr - 1];
+    std::vector<char> wraps((size_t)R, 0);
+    for (int x = 0; x < R; ++x)
+      for (int d = 0; d < a.ra; ++d) {
+        if (a.P[d][a.rr - 1] == 0) continue;
+        const int64_t b = pmod64((int64_t)a.o[d] + (int64_t)a.P[d][a.rr - 1] * x, a.S[d]);
+        if (b + a.lo[d] < 0 || b + a.hi[d] >= a.S[d]) wraps[(size_t)x] = 1;
+      }
+    for (int x = 0; x < R; ++x)
+      if (wraps[(size_t)x] && !wraps[(size_t)((x + R - 1) % R)]) {
+        a.rot = x;
+        break;
+      }
+  }
   // the table: ioff, ifd, packed weight pairs, bias + 128, ooff, ofd
   std::vector<int32_t> tab(ioff);
   a.t_ifd = (int32_t)tab.size();

@@ -41,6 +41,11 @@ struct LinearArgs {
   //   ooff[NOUT], ofd[ro][NOUT]    output pattern offsets as for the input
   const int32_t* tab;
   int32_t t_ifd, t_w, t_bias, t_ooff, t_ofd;  // offsets (int32 entries) of the table's parts
+  // Point-by-point kernel, rows of at most kLinThreads points: thread t takes
+  // point (t + rot) mod R[rr - 1] of its row (a bijection), so that the points
+  // whose pattern crosses a border, a cyclic run along the row, share one
+  // wave instead of diverging two. 0 otherwise.
+  int32_t rot;
 };
 
 // Staged form: a workgroup takes C = kLinThreads * ppt consecutive points of

@@ -48,12 +48,14 @@ typedef __attribute__((address_space(1))) uint8_t* lin_out_t;
 // pattern stays inside the array uses constant flat offsets, one that crosses
 // a border wraps each axis.
 template <int NOUT>
-__device__ __forceinline__ void linear_points(const LinearArgs& a, const int (&r0)[kLinRank], int xb, int xe) {
+__device__ __forceinline__ void linear_points(const LinearArgs& a, const int (&r0)[kLinRank], int xb, int xe,
+                                              int rot = 0) {
   const int last = a.rr - 1;
   int r[kLinRank];
 #pragma unroll
   for (int k = 0; k < kLinRank; ++k) r[k] = r0[k];
-  r[last] = xb + (int)threadIdx.x;
+  r[last] = xb + (int)threadIdx.x + rot;  // rot: only with xb = 0 and one point per thread
+  if (r[last] >= a.R[last]) r[last] -= a.R[last];
   // wrapped base points of the thread's first point, input and output
   int b[kLinRank] = {0, 0, 0, 0}, ob[kLinRank] = {0, 0, 0, 0};
 #pragma unroll
@@ -190,7 +192,7 @@ template <int NOUT>
 __global__ __launch_bounds__(kLinThreads) void k_linear(LinearArgs a) {
   int r[kLinRank];
   linear_row(a, blockIdx.x, r);
-  linear_points<NOUT>(a, r, 0, a.R[a.rr - 1]);  // no barrier in this kernel
+  linear_points<NOUT>(a, r, 0, a.R[a.rr - 1], a.rot);  // no barrier in this kernel
 }
 
 // The staged form (one workgroup per chunk of C = kLinThreads * ppt points of
