@@ -110,6 +110,21 @@ def test_non_separable_2d_polyphase(h, w, p, q, T):
     np.testing.assert_array_equal(Y, _oracle(X, tin, tout, rep, W, None))
 
 
+@pytest.mark.parametrize("rx,shift", [(255, 0), (256, 0), (257, 0), (200, 8 * 97), (256, 8 * 131 + 3)])
+def test_rows_around_one_point_per_thread(rx, shift):
+    """Rows of 255, 256 and 257 repetitions (the point-by-point kernel rotates a row's points over
+    its threads only while each thread takes one point), and input origins moved along the row so
+    that the points whose window crosses the left or right edge sit inside the row."""
+    h, w, p, q, T = 19, 8 * rx, 3, 8, 11
+    X = synthgen.uniform_frame(rx + shift, h, w)
+    rep, tin, tout, _, _ = synthgen.polyphase2d_tilers(h, w, p, q, T)
+    tin = synthgen.TilerSpec(tin.array_shape, (tin.origin[0], tin.origin[1] + shift), tin.paving, tin.fitting,
+                             tin.pat_shape)
+    W = synthgen.polyphase2d_weights(rx, p, q, T)
+    Y = _run(X, tin, tout, rep, W, None)
+    np.testing.assert_array_equal(Y, _oracle(X, tin, tout, rep, W, None))
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_random_tilers_and_weights(seed):
     """Random signed-permutation pavings with strides and a shear, fittings along distinct axes
